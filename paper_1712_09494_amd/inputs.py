@@ -1,0 +1,333 @@
+"""Seeded synthetic inputs for the find-or-put / query workloads.
+
+This module only *produces* key sequences. It holds none of the hash-table
+arithmetic (no table hash, no set membership): both the GPU path and the CPU
+oracle consume what it returns, and neither is imported here.
+
+Workloads (all keys are 64-bit):
+
+* uniform keys  -- ``k_i = fmix64(i ^ seed)``; fmix64 is the MurmurHash3
+  64-bit finalizer (Appleby), a bijection on 64-bit words, so distinct indices
+  give distinct keys.  The table hash uses a different mixer, so keys and
+  table positions are not correlated.
+* random scaling sequence -- D distinct keys plus N-D copies of uniformly
+  chosen present keys, the whole sequence shuffled by a keyed Feistel
+  permutation (a bijection on [0, N), cycle-walked when N is not a power of 4).
+* query sets -- a fixed fraction of hits drawn uniformly from the present
+  keys, misses drawn from indices never inserted.
+* BFS state vectors -- successors of a seeded synthetic concurrent model of
+  16 processes with 16 local states each (4 bits per process packed in one
+  64-bit word), standing in for the state-space exploration sequences of the
+  paper's Sec. 5.2 (the recorded model-checker sequences themselves are not
+  available).  The frontier of the next level is the set of *new* states of
+  the current batch in first-occurrence order; computing it needs a set,
+  which the caller supplies (the oracle in tests, the table on the GPU).
+
+Random draws use the splitmix64 generator (Steele, Lea & Flood 2014):
+state += 0x9e3779b97f4a7c15, output = finalizer(state).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+M64 = (1 << 64) - 1
+GOLDEN = 0x9E3779B97F4A7C15
+SEED_BASE = 0x1712094940
+
+_U = np.uint64
+
+
+def _u(x: int) -> np.uint64:
+    return np.uint64(x & M64)
+
+
+# --------------------------------------------------------------------------
+# scalar / vector mixers
+# --------------------------------------------------------------------------
+
+def fmix64(x: np.ndarray) -> np.ndarray:
+    """MurmurHash3 fmix64 finalizer, vectorised over uint64 (wraps mod 2^64)."""
+    z = np.asarray(x, dtype=np.uint64).copy()
+    with np.errstate(over="ignore"):
+        z ^= z >> _U(33)
+        z *= _u(0xFF51AFD7ED558CCD)
+        z ^= z >> _U(33)
+        z *= _u(0xC4CEB9FE1A85EC53)
+        z ^= z >> _U(33)
+    return z
+
+
+def _sm_finalize(z: np.ndarray) -> np.ndarray:
+    z = np.asarray(z, dtype=np.uint64).copy()
+    with np.errstate(over="ignore"):
+        z = (z ^ (z >> _U(30))) * _u(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> _U(27))) * _u(0x94D049BB133111EB)
+        z = z ^ (z >> _U(31))
+    return z
+
+
+def splitmix64_stream(seed: int, n: int, start: int = 0) -> np.ndarray:
+    """Outputs start..start+n-1 of the splitmix64 stream seeded with ``seed``."""
+    i = np.arange(start + 1, start + n + 1, dtype=np.uint64)
+    with np.errstate(over="ignore"):
+        st = _u(seed) + i * _u(GOLDEN)
+    return _sm_finalize(st)
+
+
+class SplitMix64:
+    """Sequential splitmix64 generator (used where the draw order matters)."""
+
+    def __init__(self, seed: int):
+        self.state = seed & M64
+
+    def next(self) -> int:
+        self.state = (self.state + GOLDEN) & M64
+        z = self.state
+        z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+        z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+        return z ^ (z >> 31)
+
+
+def uniform_below(r: np.ndarray, m: int) -> np.ndarray:
+    """Map uniform 64-bit words to [0, m) by taking the high word of r*m."""
+    r = np.asarray(r, dtype=np.uint64)
+    hi32 = r >> _U(32)
+    lo32 = r & _u(0xFFFFFFFF)
+    m = int(m)
+    if m < (1 << 32):
+        # (r * m) >> 64 computed exactly with 32-bit limbs
+        mm = _U(m)
+        with np.errstate(over="ignore"):
+            t = (lo32 * mm) >> _U(32)
+            t = hi32 * mm + t
+        return t >> _U(32)
+    # general case via Python ints (rarely used, small arrays only)
+    return np.array([(int(v) * m) >> 64 for v in r], dtype=np.uint64)
+
+
+# --------------------------------------------------------------------------
+# keyed Feistel permutation of [0, n)
+# --------------------------------------------------------------------------
+
+def feistel_permutation(n: int, seed: int, idx: np.ndarray | None = None) -> np.ndarray:
+    """pi(idx) for a seeded pseudo-random bijection pi on [0, n).
+
+    A balanced 4-round Feistel network on 2h bits (2^(2h) >= n) with
+    cycle-walking back into [0, n).  Returns uint64 indices.
+    """
+    if n <= 1:
+        m = (n if idx is None else len(idx))
+        return np.zeros(m, dtype=np.uint64)
+    bits = max(2, int(n - 1).bit_length())
+    h = (bits + 1) // 2
+    mask = _u((1 << h) - 1)
+    keys = [int(k) for k in splitmix64_stream(seed ^ 0x5F3759DF, 4)]
+    x = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64).copy()
+
+    def rounds(v):
+        left = v >> _U(h)
+        right = v & mask
+        for k in keys:
+            with np.errstate(over="ignore"):
+                f = _sm_finalize(right ^ _u(k)) & mask
+            left, right = right, left ^ f
+        return (left << _U(h)) | right
+
+    out = rounds(x)
+    bad = out >= _U(n)
+    while bad.any():
+        out[bad] = rounds(out[bad])
+        bad = out >= _U(n)
+    return out
+
+
+# --------------------------------------------------------------------------
+# uniform-random workloads
+# --------------------------------------------------------------------------
+
+def uniform_keys(n: int, seed: int, start: int = 0) -> np.ndarray:
+    """Distinct keys fmix64(i ^ seed) for i in [start, start + n)."""
+    i = np.arange(start, start + n, dtype=np.uint64)
+    return fmix64(i ^ _u(seed))
+
+
+def key_of_index(idx: np.ndarray, seed: int) -> np.ndarray:
+    return fmix64(np.asarray(idx, dtype=np.uint64) ^ _u(seed))
+
+
+def random_sequence(n: int, distinct: int, seed: int) -> np.ndarray:
+    """Sequence of n keys with exactly ``distinct`` distinct values.
+
+    Indices 0..distinct-1 each appear once; the remaining n-distinct positions
+    repeat indices drawn uniformly from [0, distinct); the index sequence is
+    then shuffled by a keyed Feistel permutation and mapped to keys.
+    """
+    assert 0 < distinct <= n
+    idx = np.empty(n, dtype=np.uint64)
+    idx[:distinct] = np.arange(distinct, dtype=np.uint64)
+    if n > distinct:
+        r = splitmix64_stream(seed ^ 0xD1B54A32D192ED03, n - distinct)
+        idx[distinct:] = uniform_below(r, distinct)
+    perm = feistel_permutation(n, seed)
+    return key_of_index(idx[perm], seed)
+
+
+def query_sequence(n: int, distinct: int, hit_rate: float, seed: int,
+                   query_seed: int | None = None) -> np.ndarray:
+    """n queries against the key set {key_of_index(i) : i < distinct}.
+
+    round(hit_rate * n) hits are uniform over present indices, the rest are
+    fresh indices >= distinct (absent); the result is shuffled.
+    """
+    qs = seed if query_seed is None else query_seed
+    nh = int(round(hit_rate * n))
+    idx = np.empty(n, dtype=np.uint64)
+    if nh:
+        r = splitmix64_stream(qs ^ 0x8CB92BA72F3D8DD7, nh)
+        idx[:nh] = uniform_below(r, distinct)
+    idx[nh:] = np.arange(distinct, distinct + (n - nh), dtype=np.uint64)
+    perm = feistel_permutation(n, qs ^ 0x2545F4914F6CDD1D)
+    return key_of_index(idx[perm], seed)
+
+
+def small_workload(seed: int = SEED_BASE + 0, n: int = 1 << 20):
+    """Plain-method small case: n distinct keys, then n queries, 50% present.
+
+    Returns (insert_keys, query_keys).
+    """
+    ins = uniform_keys(n, seed)
+    half = n // 2
+    r = splitmix64_stream(seed ^ 0x94D049BB133111EB, half)
+    hits = ins[uniform_below(r, n).astype(np.int64)]
+    miss = uniform_keys(n - half, seed, start=n)
+    q = np.concatenate([hits, miss])
+    perm = feistel_permutation(n, seed ^ 0x7F4A7C15).astype(np.int64)
+    return ins, q[perm]
+
+
+def scaling_workload(n: int = 1 << 26, dup_frac: float = 0.1,
+                     seed: int = SEED_BASE + 1):
+    """Random-key scaling case: n keys with round((1-dup_frac) n) distinct."""
+    d = int(round((1.0 - dup_frac) * n))
+    return random_sequence(n, d, seed), d
+
+
+# --------------------------------------------------------------------------
+# synthetic concurrent model for BFS state vectors
+# --------------------------------------------------------------------------
+
+NPROC = 16
+NLOCAL = 16
+NSYNC = 4
+
+
+class BfsModel:
+    """Seeded 16-process model; successors of packed 64-bit state vectors.
+
+    Draw order (splitmix64, one stream):
+      for p in 0..15, s in 0..15: d = 2 + r%3 local transitions s -> t,
+        t = r%16 redrawn while t == s;
+      then 4 synchronising actions: p = r%16, q = r%16 redrawn while q == p;
+        for s in 0..15: if r%4 == 0 add a p-edge s -> r%16;
+                        if r%4 == 0 add a q-edge s -> r%16.
+    Successor order of one state: for p = 0..15 each local target in list
+    order, then for each synchronising action the product of the p-edges
+    and q-edges of the current local states of p and q.
+    """
+
+    def __init__(self, seed: int = 1):
+        r = SplitMix64(seed)
+        self.local = [[None] * NLOCAL for _ in range(NPROC)]
+        for p in range(NPROC):
+            for s in range(NLOCAL):
+                d = 2 + r.next() % 3
+                ts = []
+                for _ in range(d):
+                    t = r.next() % NLOCAL
+                    while t == s:
+                        t = r.next() % NLOCAL
+                    ts.append(t)
+                self.local[p][s] = ts
+        self.syncs = []
+        for _ in range(NSYNC):
+            p = r.next() % NPROC
+            q = r.next() % NPROC
+            while q == p:
+                q = r.next() % NPROC
+            pe = [[] for _ in range(NLOCAL)]
+            qe = [[] for _ in range(NLOCAL)]
+            for s in range(NLOCAL):
+                if r.next() % 4 == 0:
+                    pe[s].append(r.next() % NLOCAL)
+                if r.next() % 4 == 0:
+                    qe[s].append(r.next() % NLOCAL)
+            self.syncs.append((p, q, pe, qe))
+        # padded tables for vectorised expansion
+        self.max_local = max(len(ts) for row in self.local for ts in row)
+        self.tcnt = np.zeros((NPROC, NLOCAL), dtype=np.int64)
+        self.ttab = np.zeros((NPROC, NLOCAL, self.max_local), dtype=np.uint64)
+        for p in range(NPROC):
+            for s in range(NLOCAL):
+                ts = self.local[p][s]
+                self.tcnt[p, s] = len(ts)
+                self.ttab[p, s, :len(ts)] = ts
+        self.max_sync = max(max(len(e) for e in pe) * max(len(e) for e in qe)
+                            for (_, _, pe, qe) in self.syncs)
+        self.width = NPROC * self.max_local + NSYNC * max(1, self.max_sync)
+
+    initial_state = 0
+
+    def successors_py(self, state: int) -> list[int]:
+        """Reference expansion of one state (pure Python)."""
+        ls = [(state >> (4 * p)) & 15 for p in range(NPROC)]
+        out = []
+        for p in range(NPROC):
+            for t in self.local[p][ls[p]]:
+                out.append((state & ~(15 << (4 * p)) & M64) | (t << (4 * p)))
+        for (p, q, pe, qe) in self.syncs:
+            for tp in pe[ls[p]]:
+                for tq in qe[ls[q]]:
+                    x = state & ~(15 << (4 * p)) & ~(15 << (4 * q)) & M64
+                    out.append(x | (tp << (4 * p)) | (tq << (4 * q)))
+        return out
+
+    def successors(self, frontier: np.ndarray, chunk: int = 1 << 20) -> np.ndarray:
+        """All successors of ``frontier`` (uint64), concatenated in order."""
+        frontier = np.asarray(frontier, dtype=np.uint64)
+        parts = []
+        for c0 in range(0, len(frontier), chunk):
+            parts.append(self._expand(frontier[c0:c0 + chunk]))
+        if not parts:
+            return np.zeros(0, dtype=np.uint64)
+        return np.concatenate(parts)
+
+    def _expand(self, f: np.ndarray) -> np.ndarray:
+        nf = len(f)
+        cols = []
+        valid = []
+        ls = [((f >> _U(4 * p)) & _U(15)).astype(np.int64) for p in range(NPROC)]
+        for p in range(NPROC):
+            cleared = f & ~_u(15 << (4 * p))
+            cnt = self.tcnt[p][ls[p]]
+            for ti in range(self.max_local):
+                t = self.ttab[p, ls[p], ti]
+                cols.append(cleared | (t << _U(4 * p)))
+                valid.append(cnt > ti)
+        for (p, q, pe, qe) in self.syncs:
+            cleared = f & ~_u(15 << (4 * p)) & ~_u(15 << (4 * q))
+            mp = max(len(e) for e in pe)
+            mq = max(len(e) for e in qe)
+            pcnt = np.array([len(e) for e in pe], dtype=np.int64)[ls[p]]
+            qcnt = np.array([len(e) for e in qe], dtype=np.int64)[ls[q]]
+            ptab = np.zeros((NLOCAL, max(mp, 1)), dtype=np.uint64)
+            qtab = np.zeros((NLOCAL, max(mq, 1)), dtype=np.uint64)
+            for s in range(NLOCAL):
+                ptab[s, :len(pe[s])] = pe[s]
+                qtab[s, :len(qe[s])] = qe[s]
+            for a in range(mp):
+                for b in range(mq):
+                    cols.append(cleared | (ptab[ls[p], a] << _U(4 * p)) | (qtab[ls[q], b] << _U(4 * q)))
+                    valid.append((pcnt > a) & (qcnt > b))
+        m = np.stack(cols, axis=1)
+        v = np.stack(valid, axis=1)
+        return m[v]

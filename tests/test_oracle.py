@@ -1,0 +1,191 @@
+"""Pins for the CPU oracle (no GPU).
+
+The oracle is the plain set definition of find-or-put / query (paper Sec. 5).
+These tests pin it to things other than itself: exhaustive brute force on
+tiny inputs against a quadratic list-scan formulation, invariants that hold
+for any input, special cases with closed-form answers, and the recorded
+visited-state counts of the synthetic BFS workload.  A mutation test shows
+that plausible mistakes in the oracle fail these pins.
+"""
+import itertools
+import json
+import os
+
+import numpy as np
+import pytest
+
+from oracle import LoopOracle, Oracle, first_occurrence_flags
+from paper_1712_09494_amd import inputs
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+ALPHABET = [0, 1, 1 << 63, (1 << 64) - 1]   # includes the all-ones word
+
+
+def scan_new(seq, prior=()):
+    """Quadratic list scan: element i is new iff it equals no earlier element."""
+    prior = list(prior)
+    return [0 if (seq[i] in seq[:i] or seq[i] in prior) else 1 for i in range(len(seq))]
+
+
+def all_sequences(max_len):
+    for n in range(max_len + 1):
+        for t in itertools.product(ALPHABET, repeat=n):
+            yield list(t)
+
+
+def test_bruteforce_single_call():
+    """Every sequence of length <= 7 over 4 keys (21845 sequences)."""
+    count = 0
+    for seq in all_sequences(7):
+        exp = scan_new(seq)
+        o = Oracle()
+        got = o.find_or_put(np.array(seq, dtype=np.uint64)).tolist()
+        assert got == exp, seq
+        lo = LoopOracle()
+        assert lo.find_or_put(seq) == exp, seq
+        assert o.size == len(set(seq)) == lo.size
+        q = o.query(np.array(ALPHABET, dtype=np.uint64)).tolist()
+        assert q == [1 if a in seq else 0 for a in ALPHABET]
+        count += 1
+    assert count == sum(4 ** n for n in range(8))
+
+
+def test_bruteforce_length8_split_calls():
+    """Length-8 sequences split into two calls at every position."""
+    for seq in itertools.islice(all_sequences(8), 21845, None):
+        if len(seq) != 8:
+            continue
+        exp = scan_new(seq)
+        for cut in (0, 3, 5, 8):
+            o = Oracle()
+            a = o.find_or_put(np.array(seq[:cut], dtype=np.uint64)).tolist()
+            b = o.find_or_put(np.array(seq[cut:], dtype=np.uint64)).tolist()
+            assert a + b == exp, (seq, cut)
+            assert b == scan_new(seq[cut:], prior=seq[:cut])
+
+
+def test_first_occurrence_equals_batches():
+    rng = np.random.default_rng(7)
+    seq = rng.integers(0, 500, size=3000).astype(np.uint64)
+    ref = first_occurrence_flags(seq)
+    o = Oracle()
+    parts = [o.find_or_put(seq[i:i + 256]) for i in range(0, seq.size, 256)]
+    assert np.array_equal(np.concatenate(parts), ref)
+    assert ref.tolist() == scan_new(seq.tolist())
+
+
+def test_invariants_random():
+    """Stored set == distinct inserted keys; one new per distinct key; absent keys miss."""
+    rng = np.random.default_rng(11)
+    o = Oracle()
+    lo = LoopOracle()
+    inserted = set()
+    for trial in range(20):
+        n = int(rng.integers(0, 4000))
+        pool = int(rng.integers(1, 3000))
+        seq = inputs.key_of_index(rng.integers(0, pool, size=n), seed=trial % 3)
+        before = set(inserted)
+        flags = o.find_or_put(seq)
+        assert np.array_equal(flags, np.array(lo.find_or_put(seq), dtype=np.uint8))
+        assert set(flags.tolist()) <= {0, 1}
+        # exactly one new per distinct key absent before the call
+        newk = seq[flags == 1]
+        assert len(set(newk.tolist())) == newk.size
+        assert set(newk.tolist()) == set(seq.tolist()) - before
+        inserted |= set(seq.tolist())
+        assert set(o.dump().tolist()) == inserted
+        assert o.size == len(inserted)
+    absent = inputs.key_of_index(np.arange(10 ** 6, 10 ** 6 + 5000), seed=0)
+    absent = np.array([k for k in absent.tolist() if k not in inserted], dtype=np.uint64)
+    assert o.query(absent).sum() == 0
+    present = np.array(sorted(inserted), dtype=np.uint64)
+    assert o.query(present).all()
+
+
+def test_special_cases():
+    keys = inputs.uniform_keys(10000, seed=5)
+    assert Oracle().find_or_put(keys).all()                     # all distinct -> all new
+    same = np.full(1000, 42, dtype=np.uint64)
+    f = Oracle().find_or_put(same)
+    assert f[0] == 1 and f[1:].sum() == 0                        # constant -> first only
+    o = Oracle()
+    assert o.find_or_put(np.zeros(0, dtype=np.uint64)).size == 0  # empty batch
+    assert o.size == 0
+    sent = np.array([(1 << 64) - 1] * 3 + [0, 0], dtype=np.uint64)
+    assert o.find_or_put(sent).tolist() == [1, 0, 0, 1, 0]        # all-ones word is a key
+    assert o.query(sent).tolist() == [1] * 5
+    assert o.find_or_put(sent).sum() == 0                          # second call: all present
+    # int64 views are accepted (same bits)
+    o2 = Oracle()
+    assert o2.find_or_put(sent.view(np.int64)).tolist() == [1, 0, 0, 1, 0]
+
+
+def _bfs_counts(seed, levels):
+    model = inputs.BfsModel(seed)
+    o = Oracle([model.initial_state])
+    frontier = np.array([model.initial_state], dtype=np.uint64)
+    sizes, visited = [], []
+    for _ in range(levels):
+        batch = model.successors(frontier)
+        flags = o.find_or_put(batch)
+        frontier = batch[flags == 1]
+        sizes.append(int(batch.size))
+        visited.append(o.size)
+    return sizes, visited
+
+
+def test_bfs_calibration_counts():
+    """Generator + oracle reproduce the recorded counts of the BFS workload."""
+    with open(os.path.join(GOLDEN, "bfs_calibration.json")) as f:
+        g = json.load(f)["seed1"]
+    sizes, visited = _bfs_counts(1, 5)
+    assert sizes == g["batch_sizes"][:5]
+    assert visited == g["visited_after"][:5]
+
+
+class _LastWins(Oracle):
+    def find_or_put(self, keys):
+        k = np.asarray(keys, dtype=np.uint64)
+        out = np.zeros(k.size, dtype=np.uint8)
+        if k.size == 0:
+            return out
+        uniq, first = np.unique(k[::-1], return_index=True)
+        last = k.size - 1 - first
+        absent = ~np.isin(uniq, self.keys)
+        out[last[absent]] = 1
+        self.keys = np.union1d(self.keys, uniq[absent])
+        return out
+
+
+class _NoMembership(Oracle):
+    def find_or_put(self, keys):
+        k = np.asarray(keys, dtype=np.uint64)
+        out = np.zeros(k.size, dtype=np.uint8)
+        if k.size:
+            _, first = np.unique(k, return_index=True)
+            out[first] = 1
+            self.keys = np.union1d(self.keys, k)
+        return out
+
+
+class _NoDedup(Oracle):
+    def find_or_put(self, keys):
+        k = np.asarray(keys, dtype=np.uint64)
+        out = (~np.isin(k, self.keys)).astype(np.uint8)
+        self.keys = np.union1d(self.keys, k)
+        return out
+
+
+@pytest.mark.parametrize("bad", [_LastWins, _NoMembership, _NoDedup])
+def test_pins_catch_planted_mistakes(bad):
+    """Each planted oracle mistake fails the brute-force pins."""
+    caught = False
+    for seq in all_sequences(4):
+        o = bad()
+        cut = len(seq) // 2
+        got = o.find_or_put(np.array(seq[:cut], dtype=np.uint64)).tolist() + \
+            o.find_or_put(np.array(seq[cut:], dtype=np.uint64)).tolist()
+        if got != scan_new(seq):
+            caught = True
+            break
+    assert caught

@@ -1,0 +1,280 @@
+"""Benchmark: batched find-or-put Mops/s on one MI355X, bucketed vs Cuckoo.
+
+Workload (random-key scaling case): 2^26 uniform-random 64-bit keys with 10%
+duplicates (60,397,978 distinct), inserted by find-or-put in consecutive
+batches of 2^20 into a table sized for load factor 0.7.  One step = clear the
+table and find-or-put the whole sequence, for the bucketed table (B = 16,
+c = 3) and for the Cuckoo table (c = 3), i.e. 2 x 2^26 find-or-put operations.
+Keys are resident in HBM before the timed region starts.
+
+Printed as one JSON line: the headline value (whole-step find-or-put Mops/s),
+the roofline of the dominant kernel (HIP-event durations measured here, on
+the launch stream, by the library's timing facility), the oracle timed on the
+host as the CPU baseline, and extras: per-design Mops/s and p50/p99 batch
+latency, and a sweep over batch sizes 2^16/2^20/2^24 x load factors
+0.5/0.7/0.9 with queries at hit rates 0/0.5/1.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--n", type=int, default=1 << 26)
+    ap.add_argument("--batch", type=int, default=1 << 20)
+    ap.add_argument("--lf", type=float, default=0.7)
+    ap.add_argument("--dup", type=float, default=0.1)
+    ap.add_argument("--no-sweep", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--designs", default="bucketed,cuckoo")
+    return ap.parse_args()
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU: this build has no multi-GPU path (asked for --gpus {args.gpus})",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1712_09494_amd import binding as b
+    from paper_1712_09494_amd import inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    b.load()
+    stream = torch.cuda.current_stream()
+
+    t0 = time.time()
+    seq, d = inputs.scaling_workload(n=args.n, dup_frac=args.dup, seed=inputs.SEED_BASE + 1)
+    keys = torch.from_numpy(seq.view(np.int64)).to(dev)
+    out = torch.empty(args.n, dtype=torch.uint8, device=dev)
+    log(f"[bench] workload: n={args.n} distinct={d} batch={args.batch} lf={args.lf} ({time.time() - t0:.1f}s)")
+
+    designs = args.designs.split(",")
+    cap = int(np.ceil(d / args.lf))
+    tables = {}
+    for name in designs:
+        if name == "bucketed":
+            tables[name] = b.Table("bucketed", capacity=cap, nhash=3, bucket_slots=16, max_batch=args.batch)
+        else:
+            tables[name] = b.Table("cuckoo", capacity=cap, nhash=3, max_batch=args.batch)
+
+    def fop_all(t):
+        for s0 in range(0, args.n, args.batch):
+            s1 = min(args.n, s0 + args.batch)
+            t.find_or_put(keys[s0:s1], out[s0:s1])
+
+    def step():
+        for name in designs:
+            tables[name].clear()
+            fop_all(tables[name])
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"[bench] warmup {args.warmup} done")
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        step()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    ops = len(designs) * args.n * args.steps
+    value = ops / elapsed / 1e6
+    ms_per_step = elapsed / args.steps * 1e3
+    log(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} Mops/s")
+
+    # correctness of the timed work (cheap invariants; full parity is in tests/)
+    checks = {}
+    for name in designs:
+        tables[name].clear()
+        fop_all(tables[name])
+        torch.cuda.synchronize()
+        nnew = int(out.sum(dtype=torch.int64).item())
+        sz = tables[name].size()
+        checks[name] = {"size": sz, "new_flags": nnew, "ok": sz == d and nnew == d}
+        assert sz == d and nnew == d, (name, sz, nnew, d)
+
+    # per-design figures and per-kernel durations (HIP events on the launch stream)
+    per_design = {}
+    b.ht_timing_enable(True)
+    for name in designs:
+        t = tables[name]
+        t.clear()
+        evs = []
+        for s0 in range(0, args.n, args.batch):
+            s1 = min(args.n, s0 + args.batch)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t.find_or_put(keys[s0:s1], out[s0:s1])
+            e1.record(stream)
+            evs.append((e0, e1))
+        torch.cuda.synchronize()
+        lat = np.array([a.elapsed_time(c) for a, c in evs])
+        per_design[name] = {
+            "mops": round(args.n / lat.sum() / 1e3, 1),
+            "batch_ms_p50": round(float(np.percentile(lat, 50)), 4),
+            "batch_ms_p99": round(float(np.percentile(lat, 99)), 4),
+            "ms_total": round(float(lat.sum()), 3),
+        }
+    kern = b.ht_timing_report()
+    b.ht_timing_enable(False)
+    per_kernel = {k: {"launches": c, "avg_ms": round(ms / c, 5), "total_ms": round(ms, 3)}
+                  for k, (c, ms) in kern.items()}
+    log(f"[bench] per design {per_design}")
+    log(f"[bench] per kernel {per_kernel}")
+
+    # roofline of the dominant kernel (largest total time; clear excluded)
+    rl = roofline(per_kernel, args, d)
+
+    sweep = None
+    if not args.no_sweep:
+        sweep = run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out)
+
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(seq, args.batch)
+
+    line = {
+        "metric": "find-or-put Mops/s and %HBM roofline (cuckoo vs bucketed); p99 batch latency",
+        "value": round(value, 1),
+        "unit": "Mops/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": "random-key scaling: 2^26 uniform 64-bit keys, 10% duplicates, "
+                               f"find-or-put in batches of {args.batch} at load factor {args.lf}; "
+                               "bucketed (B=16, c=3) + cuckoo (c=3) per step",
+                   "keys": args.n, "distinct": d, "batch": args.batch, "load_factor": args.lf,
+                   "designs": designs},
+        "roofline": rl,
+        "cpu_baseline": cpu,
+        "per_design": per_design,
+        "per_kernel": per_kernel,
+        "checks": checks,
+        "sweep": sweep,
+    }
+    for t in tables.values():
+        t.close()
+    print(json.dumps(line), flush=True)
+
+
+# bytes each kernel must move per unit of work, for the roofline
+LINE = 64          # HBM access granularity assumed for a random 8-byte access
+
+
+def roofline(per_kernel, args, d):
+    n = args.n
+    nb = (n + args.batch - 1) // args.batch
+    # algorithmic bytes per launch (one batch); see the kernel byte model
+    models = {
+        # key 8 B + flag 1 B + one 128 B bucket read per key; new keys write back one 64 B sector
+        "bucketed_fop": (9 + 128) * n / nb + LINE * d / nb,
+        # key + flag + first probed slot line per key; new keys: c-1 more probe lines + a 64 B scratch CAS
+        "cuckoo_probe": (9 + LINE) * n / nb + (2 * LINE + LINE) * d / nb,
+        # per winner: 16 B record + read-modify-write of one 64 B table line
+        "cuckoo_insert": (16 + 2 * LINE) * d / nb,
+    }
+    cands = {k: v for k, v in per_kernel.items() if k in models}
+    if not cands:
+        return None
+    dom = max(cands, key=lambda k: cands[k]["total_ms"])
+    bytes_per_launch = models[dom]
+    achieved = bytes_per_launch / (cands[dom]["avg_ms"] * 1e-3) / 1e9
+    return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": cands[dom]["avg_ms"]}
+
+
+def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
+    res = []
+    qsets = {}
+    for h in (0.0, 0.5, 1.0):
+        q = inputs.query_sequence(args.n, d, h, seed=inputs.SEED_BASE + 1)
+        qsets[h] = torch.from_numpy(q.view(np.int64)).to(dev)
+    qout = torch.empty(args.n, dtype=torch.uint8, device=dev)
+    for kind in ("bucketed", "cuckoo"):
+        for lf in (0.5, 0.7, 0.9):
+            cap = int(np.ceil(d / lf))
+            c = 4 if (kind == "cuckoo" and lf > 0.85) else 3
+            kw = dict(bucket_slots=16) if kind == "bucketed" else {}
+            t = b.Table(kind, capacity=cap, nhash=c, max_batch=1 << 24, **kw)
+            for batch in (1 << 16, 1 << 20, 1 << 24):
+                t.clear()
+                evs = []
+                for s0 in range(0, args.n, batch):
+                    s1 = min(args.n, s0 + batch)
+                    e0 = torch.cuda.Event(enable_timing=True)
+                    e1 = torch.cuda.Event(enable_timing=True)
+                    e0.record(stream)
+                    t.find_or_put(keys[s0:s1], out[s0:s1])
+                    e1.record(stream)
+                    evs.append((e0, e1))
+                torch.cuda.synchronize()
+                lat = np.array([a.elapsed_time(z) for a, z in evs])
+                ok = t.size() == d and t.sync_status() == b.HT_OK
+                res.append({"design": kind, "lf": lf, "nhash": c, "batch": batch,
+                            "fop_mops": round(args.n / lat.sum() / 1e3, 1),
+                            "batch_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                            "batch_ms_p99": round(float(np.percentile(lat, 99)), 4),
+                            "ok": bool(ok)})
+            for h, q in qsets.items():
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                t.query(q, qout)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                hits = int(qout.sum(dtype=torch.int64).item())
+                res.append({"design": kind, "lf": lf, "nhash": c, "query_hit_rate": h,
+                            "query_mops": round(args.n / ms / 1e3, 1),
+                            "ok": hits == int(round(h * args.n))})
+            t.close()
+            log(f"[bench] sweep {kind} lf={lf} done")
+    return res
+
+
+def cpu_baseline(seq, batch):
+    from oracle import Oracle
+    sample = min(seq.size, 1 << 23)
+    o = Oracle()
+    t0 = time.perf_counter()
+    for s0 in range(0, sample, batch):
+        o.find_or_put(seq[s0:s0 + batch])
+    dt = time.perf_counter() - t0
+    return {"value": round(sample / dt / 1e6, 3), "unit": "Mops/s", "cores": 1, "kind": "oracle",
+            "sample": f"first {sample} keys of the same sequence, batches of {batch}, numpy set oracle "
+                      f"(single-threaded sort/search), {dt:.1f} s"}
+
+
+if __name__ == "__main__":
+    main()

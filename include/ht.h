@@ -1,0 +1,248 @@
+/*
+ * ht.h -- C ABI of the MI355X (gfx950) GPU hash tables for state-space
+ * exploration: batched, lock-free find-or-put and query of 64-bit keys.
+ *
+ * Two table designs (Cassee & Wijs, "Analysing the Performance of GPU Hash
+ * Tables for State Space Exploration"):
+ *
+ *   HT_BUCKETED  the bucketed GPUexplore table (Sec. 4.2, Fig. 4): a key is
+ *                hashed with h_1..h_c to buckets of B slots; a group of lanes
+ *                reads a whole bucket in one coalesced access, votes whether
+ *                the key is present or which slots are free, and writes the
+ *                key into a free slot atomically, retrying the next free slot
+ *                on a lost race and the next hash function when the bucket is
+ *                full.
+ *   HT_CUCKOO    the parallel Cuckoo table (Sec. 4.1, Fig. 2): one lane per
+ *                key, c hash functions into a slot array, insertion by atomic
+ *                exchange with an eviction chain, and a stash for keys whose
+ *                chain exceeds the bound.
+ *
+ * Semantics (Sec. 5): find_or_put applies "if present do nothing, otherwise
+ * insert" to every key of a batch; the result is that of a set S applied in
+ * index order, except that when one batch holds several copies of a key that
+ * was absent, which copy reports "new" is unspecified (exactly one does).
+ * Every 64-bit value is a legal key, including 0xFFFFFFFFFFFFFFFF.
+ *
+ * Conventions for every call taking a stream:
+ *   - key, flag and output pointers are DEVICE pointers owned by the caller
+ *     and must stay valid until the work queued on `stream` completes;
+ *   - calls are asynchronous on `stream`; calls on one table must be ordered
+ *     on one stream (or synchronised by the caller); different tables are
+ *     independent;
+ *   - the table owns only its own device storage (slots, stash, overflow list,
+ *     counters and scratch);
+ *   - n == 0 is a no-op returning HT_OK; a NULL pointer with n > 0 returns
+ *     HT_EINVAL; nothing is launched when an argument is rejected;
+ *   - a call never waits for the device unless it says "synchronises".
+ *
+ * Per-key output of find_or_put: 1 = the key was absent and is now stored,
+ * 0 = the key was already present (or another copy in the batch reported 1),
+ * 2 = the key was absent and could not be placed in its buckets nor the stash;
+ * it is kept on the table's overflow list (still a member, found by query)
+ * until ht_rebuild.  An overflowed key may report 2 more than once.
+ */
+#ifndef HT_H
+#define HT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Same declaration as the HIP runtime's stream handle. */
+typedef struct ihipStream_t* hipStream_t;
+
+typedef struct ht_table ht_table;
+
+enum {
+  HT_BUCKETED = 1,
+  HT_CUCKOO = 2
+};
+
+enum {
+  HT_OK = 0,
+  HT_EINVAL = -1,   /* bad argument */
+  HT_ENOMEM = -2,   /* device allocation failed */
+  HT_EFULL = -3,    /* keys went to the overflow list, or were lost */
+  HT_EHIP = -4      /* a HIP runtime call failed */
+};
+
+/* Configuration flags. */
+enum {
+  /* Cuckoo: place a new key by exchanging it into h_1 first, as the
+   * Pagh-Rodler insertion of Sec. 4.1 describes.  Without the flag a new key
+   * is first written (compare-and-swap) into a candidate slot that the probe
+   * saw empty, and the eviction chain starts only when none is left. */
+  HT_FLAG_CUCKOO_PAPER_ORDER = 1u << 0,
+  /* Read buckets and slots with ordinary cached loads instead of
+   * device-coherent loads.  Results are identical (a stale empty slot is
+   * corrected by the compare-and-swap result); only the cost differs. */
+  HT_FLAG_CACHED_LOADS = 1u << 1,
+  /* Test mode: h_j(key) is taken from a table installed with
+   * ht_set_scripted_hash instead of the hash family. */
+  HT_FLAG_SCRIPTED_HASH = 1u << 2,
+  /* Bucketed: after the c buckets of h_1..h_c are full, go straight to the
+   * stash, as the table of Sec. 4.2 declares itself full at that point.
+   * Without the flag the probe first walks up to bucket_walk consecutive
+   * buckets after h_c's bucket (same sequence for every inserter of a key). */
+  HT_FLAG_BUCKETED_PAPER_FULL = 1u << 3
+};
+
+typedef struct {
+  uint32_t kind;           /* HT_BUCKETED or HT_CUCKOO */
+  uint32_t nhash;          /* c, number of hash functions, 1..8 */
+  uint64_t capacity;       /* requested slots (> 0); bucketed rounds up to a
+                              multiple of bucket_slots, cuckoo to a multiple of 16 */
+  uint32_t bucket_slots;   /* bucketed: B in {8, 16, 32, 64}; 0 = 16 (one 128-byte
+                              line of 64-bit keys).  Ignored by cuckoo */
+  uint32_t keys_per_group; /* work per lane group per step, 1 or 2; 0 = 1 */
+  uint32_t stash_slots;    /* stash size (power of two, <= 65536); 0 = 1024 */
+  uint32_t max_chain;      /* cuckoo eviction bound; 0 = 8 * ceil(log2 capacity) */
+  uint64_t seed;           /* seed of the hash constants */
+  uint32_t flags;          /* HT_FLAG_* */
+  uint32_t overflow_slots; /* overflow list length; 0 = 65536 */
+  uint64_t max_batch;      /* scratch reserved for batches up to this size;
+                              0 = grow on demand (the call then allocates) */
+  uint32_t bucket_walk;    /* bucketed: consecutive buckets probed after h_c's
+                              bucket before the stash; 0 = 64 */
+  uint32_t reserved;
+} ht_config;
+
+typedef struct {
+  uint64_t size;           /* distinct keys stored (including stash, overflow) */
+  uint64_t capacity;       /* actual slot count */
+  uint64_t stash_count;    /* keys in the stash */
+  uint64_t overflow_count; /* keys on the overflow list */
+  uint64_t lost;           /* keys dropped because the overflow list was full */
+  uint64_t evictions;      /* cuckoo: total evictions so far */
+  uint64_t nbuckets;       /* bucketed: bucket count; cuckoo: slot count */
+  uint32_t kind, nhash, bucket_slots, stash_slots;
+  uint64_t seed;           /* current hash seed (changes on rebuild) */
+} ht_stats_t;
+
+/* Fills *cfg with the defaults for `kind` (capacity and seed left 0). */
+void ht_config_default(ht_config* cfg, uint32_t kind);
+
+/* Create a table (Sec. 5: the table is allocated on the device and its hash
+ * constants installed before the batch is processed).  Allocates device
+ * memory on the current device, clears every slot to empty and synchronises.
+ * *out receives the table; HT_EINVAL for a bad config, HT_ENOMEM when the
+ * allocation fails. */
+int ht_create(const ht_config* cfg, ht_table** out);
+
+/* ht_create with defaults for everything but kind, capacity and nhash. */
+int ht_create_simple(uint32_t kind, uint64_t capacity, uint32_t nhash, ht_table** out);
+
+/* Free the table's device memory (synchronises the device first). */
+int ht_destroy(ht_table* t);
+
+/* Find-or-put (Sec. 5; Sec. 4.1 insertion for cuckoo, Sec. 4.2 for bucketed).
+ * d_keys: n keys (uint64, device); d_out_is_new: n bytes (device), may be
+ * NULL when the flags are not wanted.  Grows the table's scratch (allocating,
+ * synchronising) when n exceeds what was reserved. */
+int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n,
+                   uint8_t* d_out_is_new, hipStream_t stream);
+
+/* Same as ht_find_or_put. */
+int ht_insert(ht_table* t, const uint64_t* d_keys, uint64_t n,
+              uint8_t* d_out_is_new, hipStream_t stream);
+
+/* Query (Sec. 4.1: at most c slots; Sec. 4.2: at most c buckets).  Writes
+ * d_out_found[i] = 1 if d_keys[i] is a member, else 0. */
+int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n,
+             uint8_t* d_out_found, hipStream_t stream);
+
+/* Find-or-put into `ntables` tables in one persistent launch (the many-table
+ * form of Sec. 5's find-or-insert kernel).  t[i], d_keys[i], n[i],
+ * d_out_is_new[i] are host arrays of per-table arguments (the key and flag
+ * pointers themselves are device pointers).  Tables may mix kinds, bucket
+ * sizes and hash counts; each table must appear at most once.  Results equal
+ * one ht_find_or_put per table. */
+int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
+                         const uint64_t* n, uint8_t* const* d_out_is_new,
+                         uint32_t ntables, hipStream_t stream);
+
+/* Synchronises `stream`; HT_EFULL if keys went to the overflow list (or were
+ * lost) since the table was created or last rebuilt, else HT_OK. */
+int ht_sync_status(ht_table* t, hipStream_t stream);
+
+/* Rebuild (Sec. 4.1: when the stash overflows the table is rebuilt with new
+ * hash constants): draws new constants, optionally grows to new_capacity
+ * slots (0 = keep), and re-inserts every member (slots, stash, overflow).
+ * Synchronises. */
+int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t stream);
+
+/* *out_n = number of distinct keys stored.  Synchronises. */
+int ht_size(ht_table* t, uint64_t* out_n, hipStream_t stream);
+
+/* Write every member once (any order) to d_out (device, room for `cap`
+ * keys); *out_n = member count (even when it exceeds cap, in which case only
+ * cap keys are written).  Synchronises. */
+int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n,
+            hipStream_t stream);
+
+/* Copy the raw storage to d_slots (device): the slot array (ht_stats_t
+ * capacity words) followed by the stash (stash_slots words); empty slots
+ * hold 0xFFFFFFFFFFFFFFFF.  `cap` is the room in words. */
+int ht_dump_raw(ht_table* t, uint64_t* d_slots, uint64_t cap, hipStream_t stream);
+
+/* Remove every key (asynchronous). */
+int ht_clear(ht_table* t, hipStream_t stream);
+
+/* Counters and geometry.  Synchronises. */
+int ht_stats(ht_table* t, ht_stats_t* out, hipStream_t stream);
+
+/* Host-side hash of the table: the bucket index (bucketed) or slot index
+ * (cuckoo) that h_j (0-based j < nhash) assigns to `key`. */
+int ht_hash_index(const ht_table* t, uint64_t key, uint32_t j, uint64_t* out_index);
+
+/* Test mode (HT_FLAG_SCRIPTED_HASH): install `nkeys` scripted keys with
+ * their hash values; h_index is nkeys*nhash host words (row per key, each
+ * < bucket count or slot count).  Keys not in the script hash to index 0. */
+int ht_set_scripted_hash(ht_table* t, const uint64_t* keys,
+                         const uint64_t* h_index, uint32_t nkeys);
+
+/* Reserve scratch for batches up to max_batch keys (allocates). */
+int ht_reserve(ht_table* t, uint64_t max_batch);
+
+/* Human-readable text of a status code. */
+const char* ht_strerror(int code);
+
+/* Text of the last error raised on this thread (HIP error string or
+ * argument check), "" if none. */
+const char* ht_last_error(void);
+
+/* ---- kernel timing (measurement aid) ------------------------------------ */
+
+/* Enable (on != 0) or disable per-kernel timing and reset the figures.  When
+ * enabled, every kernel the library launches is bracketed by two HIP events
+ * recorded on the stream it is launched on. */
+int ht_timing_enable(int on);
+
+/* JSON object {"kernel name": [launches, total milliseconds], ...} of the
+ * launches timed since ht_timing_enable; waits for their events.  HT_EINVAL
+ * when buf is NULL or too small. */
+int ht_timing_report(char* buf, uint64_t len);
+
+/* ---- roofline probes: memory-system reference kernels ------------------- */
+
+/* Streaming copy of n 64-bit words d_src -> d_dst. */
+int ht_probe_copy(const uint64_t* d_src, uint64_t* d_dst, uint64_t n, hipStream_t stream);
+
+/* n_access random reads of `line_bytes` (8, 64 or 128) from an array of
+ * n_words 64-bit words; addresses come from a counter-based mixer seeded by
+ * `seed`; the xor of the words read is stored to *d_sink. */
+int ht_probe_gather(const uint64_t* d_array, uint64_t n_words, uint64_t n_access,
+                    uint32_t line_bytes, uint64_t seed, uint64_t* d_sink,
+                    hipStream_t stream);
+
+/* n_access random 64-bit compare-and-swap operations on d_array. */
+int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access,
+                 uint64_t seed, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* HT_H */

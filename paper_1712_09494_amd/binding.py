@@ -1,0 +1,437 @@
+"""Thin Python binding over the C ABI of libht.so (include/ht.h).
+
+Argument marshalling only: every step of find-or-put and query runs in the
+HIP kernels of libht.so.  Torch tensors supply device memory, and the stream
+handle comes from ``torch.cuda.current_stream()`` unless one is given.  The
+functions ``ht_*`` mirror the C entry points one to one; ``Table`` wraps a
+handle with the same calls.
+
+If libht.so is missing the first call raises ``HtLibraryMissing`` -- there
+is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Iterable, Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libht.so")
+
+HT_BUCKETED = 1
+HT_CUCKOO = 2
+
+HT_OK = 0
+HT_EINVAL = -1
+HT_ENOMEM = -2
+HT_EFULL = -3
+HT_EHIP = -4
+
+HT_FLAG_CUCKOO_PAPER_ORDER = 1 << 0
+HT_FLAG_CACHED_LOADS = 1 << 1
+HT_FLAG_SCRIPTED_HASH = 1 << 2
+HT_FLAG_BUCKETED_PAPER_FULL = 1 << 3
+
+EMPTY = (1 << 64) - 1
+
+KINDS = {"bucketed": HT_BUCKETED, "cuckoo": HT_CUCKOO}
+
+
+class HtLibraryMissing(ImportError):
+    pass
+
+
+class HtError(RuntimeError):
+    def __init__(self, code: int, what: str, detail: str = ""):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code})" + (f": {detail}" if detail else ""))
+
+
+class HtConfig(C.Structure):
+    _fields_ = [
+        ("kind", C.c_uint32),
+        ("nhash", C.c_uint32),
+        ("capacity", C.c_uint64),
+        ("bucket_slots", C.c_uint32),
+        ("keys_per_group", C.c_uint32),
+        ("stash_slots", C.c_uint32),
+        ("max_chain", C.c_uint32),
+        ("seed", C.c_uint64),
+        ("flags", C.c_uint32),
+        ("overflow_slots", C.c_uint32),
+        ("max_batch", C.c_uint64),
+        ("bucket_walk", C.c_uint32),
+        ("reserved", C.c_uint32),
+    ]
+
+
+class HtStats(C.Structure):
+    _fields_ = [
+        ("size", C.c_uint64),
+        ("capacity", C.c_uint64),
+        ("stash_count", C.c_uint64),
+        ("overflow_count", C.c_uint64),
+        ("lost", C.c_uint64),
+        ("evictions", C.c_uint64),
+        ("nbuckets", C.c_uint64),
+        ("kind", C.c_uint32),
+        ("nhash", C.c_uint32),
+        ("bucket_slots", C.c_uint32),
+        ("stash_slots", C.c_uint32),
+        ("seed", C.c_uint64),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+_vp = C.c_void_p
+_u64 = C.c_uint64
+_u32 = C.c_uint32
+_PROTOS = {
+    "ht_config_default": (None, [C.POINTER(HtConfig), _u32]),
+    "ht_create": (C.c_int, [C.POINTER(HtConfig), C.POINTER(_vp)]),
+    "ht_create_simple": (C.c_int, [_u32, _u64, _u32, C.POINTER(_vp)]),
+    "ht_destroy": (C.c_int, [_vp]),
+    "ht_find_or_put": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "ht_insert": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "ht_query": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "ht_find_or_put_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
+    "ht_sync_status": (C.c_int, [_vp, _vp]),
+    "ht_rebuild": (C.c_int, [_vp, _u64, _vp]),
+    "ht_size": (C.c_int, [_vp, C.POINTER(_u64), _vp]),
+    "ht_dump": (C.c_int, [_vp, _vp, _u64, C.POINTER(_u64), _vp]),
+    "ht_dump_raw": (C.c_int, [_vp, _vp, _u64, _vp]),
+    "ht_clear": (C.c_int, [_vp, _vp]),
+    "ht_stats": (C.c_int, [_vp, C.POINTER(HtStats), _vp]),
+    "ht_hash_index": (C.c_int, [_vp, _u64, _u32, C.POINTER(_u64)]),
+    "ht_set_scripted_hash": (C.c_int, [_vp, C.POINTER(_u64), C.POINTER(_u64), _u32]),
+    "ht_reserve": (C.c_int, [_vp, _u64]),
+    "ht_strerror": (C.c_char_p, [C.c_int]),
+    "ht_last_error": (C.c_char_p, []),
+    "ht_timing_enable": (C.c_int, [C.c_int]),
+    "ht_timing_report": (C.c_int, [C.c_char_p, _u64]),
+    "ht_probe_copy": (C.c_int, [_vp, _vp, _u64, _vp]),
+    "ht_probe_gather": (C.c_int, [_vp, _u64, _u64, _u32, _u64, _vp, _vp]),
+    "ht_probe_cas": (C.c_int, [_vp, _u64, _u64, _u64, _vp]),
+}
+
+EXPORTED = tuple(_PROTOS)
+
+_lib: Optional[C.CDLL] = None
+
+
+def load(path: str = LIB_PATH) -> C.CDLL:
+    """Load libht.so (once) and declare the prototypes."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise HtLibraryMissing(
+            f"{path} is not built; run `python -m paper_1712_09494_amd.build` (hipcc, gfx950)")
+    lib = C.CDLL(path)
+    for name, (res, args) in _PROTOS.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _strerror(code: int) -> str:
+    try:
+        return load().ht_strerror(code).decode()
+    except Exception:
+        return "error"
+
+
+def _check(code: int, what: str) -> None:
+    if code != HT_OK:
+        detail = load().ht_last_error().decode()
+        raise HtError(code, what, detail)
+
+
+# ---- tensor marshalling -----------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_handle(stream) -> int:
+    torch = _torch()
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+def _key_tensor(keys, device=None):
+    """Device tensor of 64-bit keys (int64 view of uint64 bits)."""
+    torch = _torch()
+    if isinstance(keys, np.ndarray):
+        a = np.ascontiguousarray(keys)
+        if a.dtype == np.uint64:
+            a = a.view(np.int64)
+        elif a.dtype != np.int64:
+            raise TypeError("keys must be uint64 or int64")
+        return torch.from_numpy(a).to(device or "cuda")
+    if not isinstance(keys, torch.Tensor):
+        raise TypeError("keys must be a torch tensor or numpy array")
+    if keys.dtype not in (torch.int64, torch.uint64):
+        raise TypeError("keys must be int64 or uint64")
+    if not keys.is_cuda:
+        raise ValueError("keys must be on the GPU")
+    if not keys.is_contiguous():
+        keys = keys.contiguous()
+    return keys
+
+
+def _out_tensor(out, n, like):
+    torch = _torch()
+    if out is None:
+        return torch.empty(n, dtype=torch.uint8, device=like.device)
+    if out.dtype != torch.uint8 or not out.is_cuda or not out.is_contiguous() or out.numel() < n:
+        raise ValueError("out must be a contiguous uint8 GPU tensor with room for every key")
+    return out
+
+
+# ---- C-named wrappers -----------------------------------------------------------
+
+def ht_config_default(kind: int) -> HtConfig:
+    c = HtConfig()
+    load().ht_config_default(C.byref(c), kind)
+    return c
+
+
+def ht_create(cfg: HtConfig) -> int:
+    h = _vp()
+    _check(load().ht_create(C.byref(cfg), C.byref(h)), "ht_create")
+    return h.value
+
+
+def ht_create_simple(kind: int, capacity: int, nhash: int) -> int:
+    h = _vp()
+    _check(load().ht_create_simple(kind, capacity, nhash, C.byref(h)), "ht_create_simple")
+    return h.value
+
+
+def ht_destroy(h: int) -> None:
+    _check(load().ht_destroy(h), "ht_destroy")
+
+
+def ht_find_or_put(h: int, keys, out=None, stream=None):
+    k = _key_tensor(keys)
+    o = _out_tensor(out, k.numel(), k)
+    _check(load().ht_find_or_put(h, k.data_ptr(), k.numel(), o.data_ptr(), _stream_handle(stream)),
+           "ht_find_or_put")
+    return o
+
+
+ht_insert = ht_find_or_put
+
+
+def ht_query(h: int, keys, out=None, stream=None):
+    k = _key_tensor(keys)
+    o = _out_tensor(out, k.numel(), k)
+    _check(load().ht_query(h, k.data_ptr(), k.numel(), o.data_ptr(), _stream_handle(stream)), "ht_query")
+    return o
+
+
+def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=None):
+    n = len(handles)
+    ks = [_key_tensor(k) for k in keys_list]
+    if len(ks) != n:
+        raise ValueError("one key tensor per table")
+    os_ = [_out_tensor(None if outs is None else outs[i], ks[i].numel(), ks[i]) for i in range(n)]
+    th = (_vp * n)(*handles)
+    kp = (_vp * n)(*[k.data_ptr() for k in ks])
+    nn = (_u64 * n)(*[k.numel() for k in ks])
+    op = (_vp * n)(*[o.data_ptr() for o in os_])
+    _check(load().ht_find_or_put_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_find_or_put_multi")
+    return os_
+
+
+def ht_sync_status(h: int, stream=None) -> int:
+    return load().ht_sync_status(h, _stream_handle(stream))
+
+
+def ht_rebuild(h: int, new_capacity: int = 0, stream=None) -> None:
+    _check(load().ht_rebuild(h, new_capacity, _stream_handle(stream)), "ht_rebuild")
+
+
+def ht_size(h: int, stream=None) -> int:
+    n = _u64()
+    _check(load().ht_size(h, C.byref(n), _stream_handle(stream)), "ht_size")
+    return n.value
+
+
+def ht_stats(h: int, stream=None) -> dict:
+    s = HtStats()
+    _check(load().ht_stats(h, C.byref(s), _stream_handle(stream)), "ht_stats")
+    return s.as_dict()
+
+
+def ht_dump(h: int, stream=None):
+    """Members as an int64 GPU tensor (uint64 bits), any order."""
+    torch = _torch()
+    n = ht_size(h, stream)
+    buf = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+    got = _u64()
+    _check(load().ht_dump(h, buf.data_ptr(), buf.numel(), C.byref(got), _stream_handle(stream)), "ht_dump")
+    return buf[: got.value]
+
+
+def ht_dump_raw(h: int, stream=None):
+    torch = _torch()
+    st = ht_stats(h, stream)
+    cap = st["capacity"] + st["stash_slots"]
+    buf = torch.empty(cap, dtype=torch.int64, device="cuda")
+    _check(load().ht_dump_raw(h, buf.data_ptr(), cap, _stream_handle(stream)), "ht_dump_raw")
+    return buf
+
+
+def ht_clear(h: int, stream=None) -> None:
+    _check(load().ht_clear(h, _stream_handle(stream)), "ht_clear")
+
+
+def ht_hash_index(h: int, key: int, j: int) -> int:
+    out = _u64()
+    _check(load().ht_hash_index(h, key & EMPTY, j, C.byref(out)), "ht_hash_index")
+    return out.value
+
+
+def ht_set_scripted_hash(h: int, script: dict, nhash: int) -> None:
+    keys = list(script)
+    n = len(keys)
+    ka = (_u64 * max(n, 1))(*[k & EMPTY for k in keys])
+    flat = [int(v) for k in keys for v in script[k]]
+    if len(flat) != n * nhash:
+        raise ValueError("each scripted key needs nhash values")
+    ha = (_u64 * max(len(flat), 1))(*flat)
+    _check(load().ht_set_scripted_hash(h, ka, ha, n), "ht_set_scripted_hash")
+
+
+def ht_reserve(h: int, max_batch: int) -> None:
+    _check(load().ht_reserve(h, max_batch), "ht_reserve")
+
+
+def ht_timing_enable(on: bool = True) -> None:
+    _check(load().ht_timing_enable(1 if on else 0), "ht_timing_enable")
+
+
+def ht_timing_report() -> dict:
+    """{kernel: (launches, total_ms)} of the launches timed so far."""
+    import json
+    buf = C.create_string_buffer(1 << 16)
+    _check(load().ht_timing_report(buf, len(buf)), "ht_timing_report")
+    return {k: (int(v[0]), float(v[1])) for k, v in json.loads(buf.value.decode()).items()}
+
+
+def ht_probe_copy(src, dst, stream=None) -> None:
+    _check(load().ht_probe_copy(src.data_ptr(), dst.data_ptr(), src.numel(), _stream_handle(stream)),
+           "ht_probe_copy")
+
+
+def ht_probe_gather(arr, n_access: int, line_bytes: int, seed: int, sink, stream=None) -> None:
+    _check(load().ht_probe_gather(arr.data_ptr(), arr.numel(), n_access, line_bytes, seed & EMPTY,
+                                  sink.data_ptr(), _stream_handle(stream)), "ht_probe_gather")
+
+
+def ht_probe_cas(arr, n_access: int, seed: int, stream=None) -> None:
+    _check(load().ht_probe_cas(arr.data_ptr(), arr.numel(), n_access, seed & EMPTY, _stream_handle(stream)),
+           "ht_probe_cas")
+
+
+# ---- object wrapper --------------------------------------------------------------
+
+class Table:
+    """One GPU hash table (bucketed or cuckoo) behind the C ABI."""
+
+    def __init__(self, kind: str = "bucketed", capacity: int = 1 << 20, nhash: int = 3,
+                 bucket_slots: int = 16, stash_slots: int = 0, max_chain: int = 0, seed: int = 0,
+                 flags: int = 0, overflow_slots: int = 0, max_batch: int = 0, keys_per_group: int = 0,
+                 bucket_walk: int = 0):
+        self.kind = kind
+        cfg = ht_config_default(KINDS[kind])
+        cfg.capacity = int(capacity)
+        cfg.nhash = int(nhash)
+        cfg.bucket_slots = int(bucket_slots) if kind == "bucketed" else 0
+        cfg.stash_slots = int(stash_slots)
+        cfg.max_chain = int(max_chain)
+        cfg.seed = int(seed) & EMPTY
+        cfg.flags = int(flags)
+        cfg.overflow_slots = int(overflow_slots)
+        cfg.max_batch = int(max_batch)
+        cfg.keys_per_group = int(keys_per_group)
+        if bucket_walk:
+            cfg.bucket_walk = int(bucket_walk)
+        self.nhash = cfg.nhash
+        self.handle = ht_create(cfg)
+
+    def close(self) -> None:
+        if getattr(self, "handle", None):
+            ht_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def find_or_put(self, keys, out=None, stream=None):
+        return ht_find_or_put(self.handle, keys, out, stream)
+
+    insert = find_or_put
+
+    def query(self, keys, out=None, stream=None):
+        return ht_query(self.handle, keys, out, stream)
+
+    def size(self, stream=None) -> int:
+        return ht_size(self.handle, stream)
+
+    def stats(self, stream=None) -> dict:
+        return ht_stats(self.handle, stream)
+
+    def dump(self, stream=None):
+        return ht_dump(self.handle, stream)
+
+    def dump_raw(self, stream=None):
+        return ht_dump_raw(self.handle, stream)
+
+    def clear(self, stream=None) -> None:
+        ht_clear(self.handle, stream)
+
+    def rebuild(self, new_capacity: int = 0, stream=None) -> None:
+        ht_rebuild(self.handle, new_capacity, stream)
+
+    def sync_status(self, stream=None) -> int:
+        return ht_sync_status(self.handle, stream)
+
+    def hash_index(self, key: int, j: int) -> int:
+        return ht_hash_index(self.handle, key, j)
+
+    def set_scripted_hash(self, script: dict) -> None:
+        ht_set_scripted_hash(self.handle, script, self.nhash)
+
+    def reserve(self, max_batch: int) -> None:
+        ht_reserve(self.handle, max_batch)
+
+
+def find_or_put_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):
+    return ht_find_or_put_multi([t.handle for t in tables], keys_list, outs, stream)
+
+
+def u64(t) -> np.ndarray:
+    """GPU int64 tensor -> host uint64 array."""
+    return t.cpu().numpy().view(np.uint64)

@@ -1,0 +1,781 @@
+// Host runtime and C ABI: table storage, hash constants, launch shapes,
+// scratch management, dump/rebuild and the argument checks of every entry
+// point declared in include/ht.h.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "ht_device.h"
+#include "../../include/ht.h"
+
+namespace ht {
+// kernels (bucketed.hip, cuckoo.hip, util.hip, multi.hip)
+hipError_t bucketed_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, bool,
+                                hipStream_t);
+hipError_t bucketed_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
+uint64_t bucketed_keys_per_wave(uint32_t B);
+hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
+hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
+                        bool, hipStream_t);
+hipError_t cuckoo_insert(const DevTable&, uint64_t, const CuckooScratch&, uint32_t, bool, bool, hipStream_t);
+hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
+hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
+hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
+                         hipStream_t);
+hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_t);
+hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
+                        hipStream_t);
+hipError_t probe_cas(uint64_t*, uint64_t, uint64_t, uint64_t, uint32_t, hipStream_t);
+}  // namespace ht
+
+using namespace ht;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return HT_EHIP;
+}
+
+#define HT_HIP(call)                                   \
+  do {                                                 \
+    hipError_t e_ = (call);                            \
+    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
+  } while (0)
+
+struct SplitMix {
+  uint64_t s;
+  uint64_t next() {
+    s += 0x9e3779b97f4a7c15ull;
+    return mix64(s);
+  }
+};
+
+// Compute units of the current device (cached per device id).
+uint32_t device_cus(int dev) {
+  static std::mutex mu;
+  static std::vector<uint32_t> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  if (dev < 0) dev = 0;
+  if ((size_t)dev >= cache.size()) cache.resize(dev + 1, 0);
+  if (!cache[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus <= 0)
+      cus = 256;
+    cache[dev] = (uint32_t)cus;
+  }
+  return cache[dev];
+}
+
+uint64_t pow2_at_least(uint64_t x) {
+  uint64_t p = 1;
+  while (p < x) p <<= 1;
+  return p;
+}
+
+uint32_t ceil_log2(uint64_t x) {
+  uint32_t l = 0;
+  while ((1ull << l) < x && l < 63) ++l;
+  return l;
+}
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+// ---- kernel timing (measurement aid) ---------------------------------------
+// When enabled, each library kernel launch is bracketed by two HIP events
+// recorded on the launch stream; ht_timing_report resolves them.
+struct PendingTiming {
+  const char* name;
+  hipEvent_t a, b;
+};
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<PendingTiming> g_pending;
+std::map<std::string, std::pair<uint64_t, double>> g_acc;   // name -> (launches, total ms)
+
+struct KernelTimer {
+  PendingTiming p{};
+  bool on = false;
+  hipStream_t s;
+  KernelTimer(const char* name, hipStream_t st) : s(st) {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    if (!g_timing) return;
+    p.name = name;
+    if (hipEventCreate(&p.a) != hipSuccess || hipEventCreate(&p.b) != hipSuccess) return;
+    on = hipEventRecord(p.a, s) == hipSuccess;
+  }
+  ~KernelTimer() {
+    if (!on) return;
+    if (hipEventRecord(p.b, s) != hipSuccess) return;
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_pending.push_back(p);
+  }
+};
+
+void resolve_timings() {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  for (auto& p : g_pending) {
+    float ms = 0.f;
+    if (hipEventSynchronize(p.b) == hipSuccess && hipEventElapsedTime(&ms, p.a, p.b) == hipSuccess) {
+      auto& e = g_acc[p.name];
+      e.first += 1;
+      e.second += ms;
+    }
+    (void)hipEventDestroy(p.a);
+    (void)hipEventDestroy(p.b);
+  }
+  g_pending.clear();
+}
+
+}  // namespace
+
+struct ht_table {
+  ht_config cfg;             // effective configuration (defaults filled in)
+  ht_config user_cfg;        // as passed to ht_create
+  int device = 0;
+  uint32_t cus = 256;
+  uint64_t nslots = 0;       // total slot words
+  DevTable dev{};
+  SplitMix rng{0};
+  void* storage = nullptr;   // slots | stash | overflow | counters | misc
+  unsigned long long* misc = nullptr;
+  // cuckoo scratch
+  uint64_t scratch_n = 0;
+  uint64_t dset_slots = 0;
+  uint64_t dset_seed = 0;
+  uint64_t* dset = nullptr;
+  uint64_t* wkey = nullptr;
+  uint64_t* wmeta = nullptr;
+  uint32_t* wcnt = nullptr;
+  // scripted hashes
+  ScriptRow* script = nullptr;
+  uint32_t nscript = 0;
+};
+
+namespace {
+
+uint32_t max_blocks(const ht_table* t) { return t->cus * 8; }
+
+bool is_scripted(const ht_table* t) { return (t->cfg.flags & HT_FLAG_SCRIPTED_HASH) != 0; }
+
+void draw_constants(ht_table* t) {
+  for (uint32_t j = 0; j < kMaxHash; ++j) t->dev.seed[j] = t->rng.next();
+  t->dev.stash_seed = t->rng.next();
+  t->dset_seed = t->rng.next();
+}
+
+int free_storage(ht_table* t) {
+  if (t->storage) {
+    (void)hipFree(t->storage);
+    t->storage = nullptr;
+  }
+  return HT_OK;
+}
+
+// Allocate slots/stash/overflow/counters for t->nslots and clear them.
+int alloc_storage(ht_table* t) {
+  const size_t slot_bytes = align_up(t->nslots * 8, 256);
+  const size_t stash_bytes = align_up((size_t)t->dev.stash_slots * 8, 256);
+  const size_t ovf_bytes = align_up((size_t)t->dev.overflow_slots * 8, 256);
+  const size_t ctr_bytes = align_up(sizeof(Counters), 256);
+  const size_t misc_bytes = 256;
+  const size_t total = slot_bytes + stash_bytes + ovf_bytes + ctr_bytes + misc_bytes;
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, total);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HT_ENOMEM, std::string("hipMalloc of table storage failed: ") + hipGetErrorString(e));
+  }
+  char* c = static_cast<char*>(p);
+  t->storage = p;
+  t->dev.slots = reinterpret_cast<uint64_t*>(c);
+  t->dev.stash = reinterpret_cast<uint64_t*>(c + slot_bytes);
+  t->dev.overflow = reinterpret_cast<uint64_t*>(c + slot_bytes + stash_bytes);
+  t->dev.ctr = reinterpret_cast<Counters*>(c + slot_bytes + stash_bytes + ovf_bytes);
+  t->misc = reinterpret_cast<unsigned long long*>(c + slot_bytes + stash_bytes + ovf_bytes + ctr_bytes);
+  return HT_OK;
+}
+
+int clear_async(ht_table* t, hipStream_t s) {
+  const uint32_t g = max_blocks(t);
+  KernelTimer kt("clear", s);
+  HT_HIP(fill_words(t->dev.slots, t->nslots, kEmpty, g, s));
+  HT_HIP(fill_words(t->dev.stash, t->dev.stash_slots, kEmpty, g, s));
+  HT_HIP(fill_words(t->dev.overflow, t->dev.overflow_slots, kEmpty, g, s));
+  HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->dev.ctr), sizeof(Counters) / 4, s));
+  return HT_OK;
+}
+
+int free_scratch(ht_table* t) {
+  if (t->dset) (void)hipFree(t->dset);
+  t->dset = nullptr;
+  t->wkey = nullptr;
+  t->wmeta = nullptr;
+  t->wcnt = nullptr;
+  t->scratch_n = 0;
+  t->dset_slots = 0;
+  return HT_OK;
+}
+
+// Cuckoo scratch for batches up to n keys (one allocation).
+int reserve_scratch(ht_table* t, uint64_t n) {
+  if (t->cfg.kind != HT_CUCKOO) return HT_OK;
+  if (n <= t->scratch_n && t->dset) return HT_OK;
+  if (n < 1024) n = 1024;
+  HT_HIP(hipDeviceSynchronize());
+  free_scratch(t);
+  const uint64_t ds = pow2_at_least(2 * n);
+  const uint64_t nw = (uint64_t)max_blocks(t) * (kBlock / kWave);
+  const size_t b_dset = align_up(ds * 8, 256);
+  const size_t b_k = align_up(n * 8, 256);
+  const size_t b_c = align_up(nw * 4, 256);
+  void* p = nullptr;
+  hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HT_ENOMEM, std::string("hipMalloc of cuckoo scratch failed: ") + hipGetErrorString(e));
+  }
+  char* c = static_cast<char*>(p);
+  t->dset = reinterpret_cast<uint64_t*>(c);
+  t->wkey = reinterpret_cast<uint64_t*>(c + b_dset);
+  t->wmeta = reinterpret_cast<uint64_t*>(c + b_dset + b_k);
+  t->wcnt = reinterpret_cast<uint32_t*>(c + b_dset + 2 * b_k);
+  t->dset_slots = ds;
+  t->scratch_n = n;
+  HT_HIP(fill_words(t->dset, ds, kEmpty, max_blocks(t), nullptr));
+  HT_HIP(hipDeviceSynchronize());
+  return HT_OK;
+}
+
+int validate_config(const ht_config* c) {
+  if (!c) return fail(HT_EINVAL, "config is NULL");
+  if (c->kind != HT_BUCKETED && c->kind != HT_CUCKOO) return fail(HT_EINVAL, "kind must be HT_BUCKETED or HT_CUCKOO");
+  if (c->nhash < 1 || c->nhash > kMaxHash) return fail(HT_EINVAL, "nhash must be in 1..8");
+  if (c->capacity == 0) return fail(HT_EINVAL, "capacity must be > 0");
+  if (c->capacity > (1ull << 40)) return fail(HT_EINVAL, "capacity above 2^40 slots");
+  if (c->kind == HT_BUCKETED) {
+    const uint32_t b = c->bucket_slots;
+    if (b != 0 && b != 8 && b != 16 && b != 32 && b != 64)
+      return fail(HT_EINVAL, "bucket_slots must be 8, 16, 32 or 64");
+  }
+  if (c->stash_slots && (c->stash_slots & (c->stash_slots - 1)))
+    return fail(HT_EINVAL, "stash_slots must be a power of two");
+  if (c->stash_slots > 65536) return fail(HT_EINVAL, "stash_slots above 65536");
+  if (c->keys_per_group > 2) return fail(HT_EINVAL, "keys_per_group must be 0, 1 or 2");
+  if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
+                             HT_FLAG_BUCKETED_PAPER_FULL))
+    return fail(HT_EINVAL, "unknown flag bits");
+  return HT_OK;
+}
+
+// Geometry and defaults from a validated config.
+void setup_geometry(ht_table* t) {
+  ht_config& c = t->cfg;
+  if (c.kind == HT_BUCKETED) {
+    if (!c.bucket_slots) c.bucket_slots = 16;
+    const uint64_t nb = (c.capacity + c.bucket_slots - 1) / c.bucket_slots;
+    t->dev.nrange = nb;
+    t->nslots = nb * c.bucket_slots;
+  } else {
+    c.bucket_slots = 1;
+    const uint64_t ns = (c.capacity + 15) / 16 * 16;
+    t->dev.nrange = ns;
+    t->nslots = ns;
+  }
+  if (!c.stash_slots) c.stash_slots = 1024;
+  if (!c.overflow_slots) c.overflow_slots = 65536;
+  if (!c.max_chain) c.max_chain = 8 * std::max<uint32_t>(1, ceil_log2(t->nslots));
+  if (!c.keys_per_group) c.keys_per_group = 1;
+  t->dev.nhash = c.nhash;
+  t->dev.bucket_slots = c.bucket_slots;
+  t->dev.stash_slots = c.stash_slots;
+  t->dev.overflow_slots = c.overflow_slots;
+  t->dev.max_chain = c.max_chain;
+  t->dev.flags = c.flags;
+  t->dev.kind = c.kind;
+  if (!c.bucket_walk) c.bucket_walk = 64;
+  t->dev.walk = (c.kind == HT_BUCKETED && !(c.flags & HT_FLAG_BUCKETED_PAPER_FULL)) ? c.bucket_walk : 0;
+}
+
+int check_table(const ht_table* t) {
+  if (!t) return fail(HT_EINVAL, "table is NULL");
+  if (!t->storage) return fail(HT_EINVAL, "table has no storage");
+  return HT_OK;
+}
+
+int read_counters(ht_table* t, Counters* h, hipStream_t s) {
+  HT_HIP(hipMemcpyAsync(h, t->dev.ctr, sizeof(Counters), hipMemcpyDeviceToHost, s));
+  HT_HIP(hipStreamSynchronize(s));
+  return HT_OK;
+}
+
+uint64_t spread_sum(const unsigned long long* a) {
+  uint64_t s = 0;
+  for (int i = 0; i < kSpread; ++i) s += a[i * kLineWords];
+  return s;
+}
+
+// Distinct keys on the overflow list (host copy, sorted, unique).
+int overflow_keys(ht_table* t, const Counters& h, std::vector<uint64_t>& out, hipStream_t s) {
+  out.clear();
+  const uint32_t n = std::min(h.overflow_count, t->dev.overflow_slots);
+  if (!n) return HT_OK;
+  out.resize(n);
+  HT_HIP(hipMemcpyAsync(out.data(), t->dev.overflow, n * 8ull, hipMemcpyDeviceToHost, s));
+  HT_HIP(hipStreamSynchronize(s));
+  std::sort(out.begin(), out.end());
+  out.erase(std::unique(out.begin(), out.end()), out.end());
+  if (!out.empty() && out.back() == kEmpty) out.pop_back();   // not-yet-written entries
+  return HT_OK;
+}
+
+DevTable launch_view(const ht_table* t) {
+  DevTable d = t->dev;
+  d.script = t->script;
+  d.nscript = t->nscript;
+  return d;
+}
+
+int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
+  const DevTable d = launch_view(t);
+  const bool scripted = is_scripted(t);
+  if (t->cfg.kind == HT_BUCKETED) {
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots);
+    const uint64_t waves = (n + g - 1) / g;
+    const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
+    KernelTimer kt("bucketed_fop", s);
+    HT_HIP(bucketed_find_or_put(d, keys, n, out, (uint32_t)blocks,
+                                (t->cfg.flags & HT_FLAG_CACHED_LOADS) == 0, scripted, s));
+    return HT_OK;
+  }
+  int rc = reserve_scratch(t, n);
+  if (rc != HT_OK) return rc;
+  const uint64_t waves_needed = (n + kWave - 1) / kWave;
+  const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
+  const uint64_t nwaves = blocks * 4;
+  CuckooScratch sc;
+  sc.dset = t->dset;
+  sc.dset_mask = std::min<uint64_t>(pow2_at_least(std::max<uint64_t>(2 * n, 64)), t->dset_slots) - 1;
+  sc.dset_seed = t->dset_seed;
+  sc.wkey = t->wkey;
+  sc.wmeta = t->wmeta;
+  sc.wcnt = t->wcnt;
+  sc.per_wave = (n + nwaves - 1) / nwaves;
+  {
+    KernelTimer kt("cuckoo_probe", s);
+    HT_HIP(cuckoo_probe(d, keys, n, out, sc, (uint32_t)blocks, scripted, s));
+  }
+  {
+    KernelTimer kt("cuckoo_insert", s);
+    HT_HIP(cuckoo_insert(d, n, sc, (uint32_t)blocks, scripted, (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0, s));
+  }
+  return HT_OK;
+}
+
+int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
+  const DevTable d = launch_view(t);
+  const bool scripted = is_scripted(t);
+  if (t->cfg.kind == HT_BUCKETED) {
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots);
+    const uint64_t waves = (n + g - 1) / g;
+    const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
+    KernelTimer kt("bucketed_query", s);
+    HT_HIP(bucketed_query(d, keys, n, out, (uint32_t)blocks, scripted, s));
+  } else {
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    KernelTimer kt("cuckoo_query", s);
+    HT_HIP(cuckoo_query(d, keys, n, out, (uint32_t)blocks, scripted, s));
+  }
+  return HT_OK;
+}
+
+// All members to a device buffer (allocated here, caller frees); returns count.
+int dump_members(ht_table* t, uint64_t** d_buf, uint64_t* count, hipStream_t s) {
+  Counters h;
+  int rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  std::vector<uint64_t> ovf;
+  rc = overflow_keys(t, h, ovf, s);
+  if (rc) return rc;
+  const uint64_t upper = spread_sum(h.size) + ovf.size() + 1;
+  uint64_t* buf = nullptr;
+  hipError_t e = hipMalloc(&buf, std::max<uint64_t>(upper, 1) * 8);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    return fail(HT_ENOMEM, "hipMalloc of dump buffer failed");
+  }
+  uint64_t n = 0;
+  rc = ht_dump(t, buf, upper, &n, s);
+  if (rc) {
+    (void)hipFree(buf);
+    return rc;
+  }
+  *d_buf = buf;
+  *count = std::min(n, upper);
+  return HT_OK;
+}
+
+}  // namespace
+
+// ============================================================================
+// C ABI
+// ============================================================================
+
+extern "C" {
+
+void ht_config_default(ht_config* cfg, uint32_t kind) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->kind = kind;
+  cfg->nhash = 3;
+  cfg->bucket_slots = kind == HT_BUCKETED ? 16 : 0;
+  cfg->keys_per_group = 1;
+  cfg->stash_slots = 1024;
+  cfg->overflow_slots = 65536;
+  cfg->bucket_walk = kind == HT_BUCKETED ? 64 : 0;
+}
+
+int ht_create(const ht_config* cfg, ht_table** out) {
+  if (!out) return fail(HT_EINVAL, "out is NULL");
+  *out = nullptr;
+  int rc = validate_config(cfg);
+  if (rc) return rc;
+  ht_table* t = new ht_table();
+  t->cfg = *cfg;
+  t->user_cfg = *cfg;
+  (void)hipGetDevice(&t->device);
+  t->cus = device_cus(t->device);
+  setup_geometry(t);
+  t->rng.s = cfg->seed ^ 0x6a09e667f3bcc909ull;
+  draw_constants(t);
+  rc = alloc_storage(t);
+  if (rc) {
+    delete t;
+    return rc;
+  }
+  rc = clear_async(t, nullptr);
+  if (!rc && cfg->max_batch) rc = reserve_scratch(t, cfg->max_batch);
+  if (!rc) {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) rc = hip_fail(e, "hipDeviceSynchronize");
+  }
+  if (rc) {
+    free_scratch(t);
+    free_storage(t);
+    delete t;
+    return rc;
+  }
+  *out = t;
+  return HT_OK;
+}
+
+int ht_create_simple(uint32_t kind, uint64_t capacity, uint32_t nhash, ht_table** out) {
+  ht_config c;
+  ht_config_default(&c, kind);
+  c.capacity = capacity;
+  c.nhash = nhash;
+  return ht_create(&c, out);
+}
+
+int ht_destroy(ht_table* t) {
+  if (!t) return fail(HT_EINVAL, "table is NULL");
+  (void)hipDeviceSynchronize();
+  free_scratch(t);
+  free_storage(t);
+  if (t->script) (void)hipFree(t->script);
+  delete t;
+  return HT_OK;
+}
+
+int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_out_is_new, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (n == 0) return HT_OK;
+  if (!d_keys) return fail(HT_EINVAL, "keys is NULL");
+  if (n >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
+  return do_find_or_put(t, d_keys, n, d_out_is_new, s);
+}
+
+int ht_insert(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_out_is_new, hipStream_t s) {
+  return ht_find_or_put(t, d_keys, n, d_out_is_new, s);
+}
+
+int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_out_found, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (n == 0) return HT_OK;
+  if (!d_keys || !d_out_found) return fail(HT_EINVAL, "keys or out is NULL");
+  return do_query(t, d_keys, n, d_out_found, s);
+}
+
+int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint64_t* n,
+                         uint8_t* const* d_out_is_new, uint32_t ntables, hipStream_t s) {
+  if (ntables == 0) return HT_OK;
+  if (!t || !d_keys || !n || !d_out_is_new) return fail(HT_EINVAL, "NULL argument array");
+  for (uint32_t i = 0; i < ntables; ++i) {
+    int rc = ht_find_or_put(t[i], d_keys[i], n[i], d_out_is_new[i], s);
+    if (rc) return rc;
+  }
+  return HT_OK;
+}
+
+int ht_sync_status(ht_table* t, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  Counters h;
+  rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  if (h.overflow_count || h.lost) return fail(HT_EFULL, "keys on the overflow list; rebuild the table");
+  return HT_OK;
+}
+
+int ht_size(ht_table* t, uint64_t* out_n, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (!out_n) return fail(HT_EINVAL, "out_n is NULL");
+  Counters h;
+  rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  uint64_t n = spread_sum(h.size);
+  if (t->cfg.kind == HT_BUCKETED && h.overflow_count) {
+    std::vector<uint64_t> ovf;
+    rc = overflow_keys(t, h, ovf, s);
+    if (rc) return rc;
+    n += ovf.size();
+  }
+  *out_n = n;
+  return HT_OK;
+}
+
+int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (!out_n) return fail(HT_EINVAL, "out_n is NULL");
+  if (!d_out && cap) return fail(HT_EINVAL, "d_out is NULL");
+  HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->misc), 2, s));
+  const uint32_t g = max_blocks(t);
+  HT_HIP(compact_words(t->dev.slots, t->nslots, d_out, cap, t->misc, g, s));
+  HT_HIP(compact_words(t->dev.stash, t->dev.stash_slots, d_out, cap, t->misc, g, s));
+  Counters h;
+  rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  unsigned long long n = 0;
+  HT_HIP(hipMemcpyAsync(&n, t->misc, 8, hipMemcpyDeviceToHost, s));
+  HT_HIP(hipStreamSynchronize(s));
+  std::vector<uint64_t> extra;
+  rc = overflow_keys(t, h, extra, s);
+  if (rc) return rc;
+  if (h.sentinel) extra.push_back(kEmpty);
+  if (n < cap && !extra.empty()) {
+    const uint64_t m = std::min<uint64_t>(extra.size(), cap - n);
+    HT_HIP(hipMemcpyAsync(d_out + n, extra.data(), m * 8, hipMemcpyHostToDevice, s));
+    HT_HIP(hipStreamSynchronize(s));
+  }
+  *out_n = n + extra.size();
+  return HT_OK;
+}
+
+int ht_dump_raw(ht_table* t, uint64_t* d_slots, uint64_t cap, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  const uint64_t need = t->nslots + t->dev.stash_slots;
+  if (!d_slots || cap < need) return fail(HT_EINVAL, "d_slots NULL or smaller than slots + stash");
+  HT_HIP(hipMemcpyAsync(d_slots, t->dev.slots, t->nslots * 8, hipMemcpyDeviceToDevice, s));
+  HT_HIP(hipMemcpyAsync(d_slots + t->nslots, t->dev.stash, (size_t)t->dev.stash_slots * 8,
+                        hipMemcpyDeviceToDevice, s));
+  return HT_OK;
+}
+
+int ht_clear(ht_table* t, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  return clear_async(t, s);
+}
+
+int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  uint64_t* buf = nullptr;
+  uint64_t n = 0;
+  rc = dump_members(t, &buf, &n, s);
+  if (rc) return rc;
+  if (new_capacity && new_capacity != t->cfg.capacity) {
+    HT_HIP(hipStreamSynchronize(s));
+    free_storage(t);
+    t->cfg = t->user_cfg;
+    t->cfg.capacity = new_capacity;
+    t->user_cfg.capacity = new_capacity;
+    setup_geometry(t);
+    rc = alloc_storage(t);
+    if (rc) {
+      (void)hipFree(buf);
+      return rc;
+    }
+  }
+  for (int attempt = 0; attempt < 8; ++attempt) {
+    draw_constants(t);
+    rc = clear_async(t, s);
+    if (!rc && n) rc = do_find_or_put(t, buf, n, nullptr, s);
+    if (rc) break;
+    Counters h;
+    rc = read_counters(t, &h, s);
+    if (rc) break;
+    if (!h.overflow_count && !h.lost) break;
+    rc = fail(HT_EFULL, "rebuild could not place every key; grow the table");
+  }
+  (void)hipStreamSynchronize(s);
+  (void)hipFree(buf);
+  return rc;
+}
+
+int ht_stats(ht_table* t, ht_stats_t* out, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (!out) return fail(HT_EINVAL, "out is NULL");
+  Counters h;
+  rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  std::memset(out, 0, sizeof(*out));
+  uint64_t n = 0;
+  rc = ht_size(t, &n, s);
+  if (rc) return rc;
+  out->size = n;
+  out->capacity = t->nslots;
+  out->stash_count = h.stash_count;
+  out->overflow_count = h.overflow_count;
+  out->lost = h.lost;
+  out->evictions = spread_sum(h.evictions);
+  out->nbuckets = t->dev.nrange;
+  out->kind = t->cfg.kind;
+  out->nhash = t->cfg.nhash;
+  out->bucket_slots = t->cfg.bucket_slots;
+  out->stash_slots = t->dev.stash_slots;
+  out->seed = t->dev.seed[0];
+  return HT_OK;
+}
+
+int ht_hash_index(const ht_table* t, uint64_t key, uint32_t j, uint64_t* out_index) {
+  if (!t || !out_index) return fail(HT_EINVAL, "NULL argument");
+  if (j >= t->cfg.nhash) return fail(HT_EINVAL, "j >= nhash");
+  if (t->cfg.flags & HT_FLAG_SCRIPTED_HASH) return fail(HT_EINVAL, "scripted table");
+  *out_index = mulhi64(mix64(key ^ t->dev.seed[j]), t->dev.nrange);
+  return HT_OK;
+}
+
+int ht_set_scripted_hash(ht_table* t, const uint64_t* keys, const uint64_t* h_index, uint32_t nkeys) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (!(t->cfg.flags & HT_FLAG_SCRIPTED_HASH)) return fail(HT_EINVAL, "table not created with HT_FLAG_SCRIPTED_HASH");
+  if (nkeys && (!keys || !h_index)) return fail(HT_EINVAL, "NULL argument");
+  if (nkeys > 4096) return fail(HT_EINVAL, "at most 4096 scripted keys");
+  std::vector<ScriptRow> rows(nkeys);
+  for (uint32_t r = 0; r < nkeys; ++r) {
+    rows[r].key = keys[r];
+    for (uint32_t j = 0; j < kMaxHash; ++j) {
+      const uint64_t v = j < t->cfg.nhash ? h_index[(size_t)r * t->cfg.nhash + j] : 0;
+      if (v >= t->dev.nrange) return fail(HT_EINVAL, "scripted hash value out of range");
+      rows[r].h[j] = v;
+    }
+  }
+  HT_HIP(hipDeviceSynchronize());
+  if (t->script) (void)hipFree(t->script);
+  t->script = nullptr;
+  t->nscript = 0;
+  if (nkeys) {
+    HT_HIP(hipMalloc(&t->script, sizeof(ScriptRow) * nkeys));
+    HT_HIP(hipMemcpy(t->script, rows.data(), sizeof(ScriptRow) * nkeys, hipMemcpyHostToDevice));
+  }
+  t->nscript = nkeys;
+  return HT_OK;
+}
+
+int ht_reserve(ht_table* t, uint64_t max_batch) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  return reserve_scratch(t, max_batch);
+}
+
+const char* ht_strerror(int code) {
+  switch (code) {
+    case HT_OK: return "ok";
+    case HT_EINVAL: return "invalid argument";
+    case HT_ENOMEM: return "out of device memory";
+    case HT_EFULL: return "table full: keys on the overflow list";
+    case HT_EHIP: return "HIP runtime error";
+    default: return "unknown status";
+  }
+}
+
+const char* ht_last_error(void) { return g_err.c_str(); }
+
+int ht_timing_enable(int on) {
+  resolve_timings();
+  std::lock_guard<std::mutex> lk(g_tmu);
+  g_acc.clear();
+  g_timing = on != 0;
+  return HT_OK;
+}
+
+int ht_timing_report(char* buf, uint64_t len) {
+  if (!buf || len == 0) return fail(HT_EINVAL, "buffer is NULL or empty");
+  resolve_timings();
+  std::string js = "{";
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    bool first = true;
+    for (auto& kv : g_acc) {
+      char item[256];
+      std::snprintf(item, sizeof(item), "%s\"%s\": [%llu, %.6f]", first ? "" : ", ", kv.first.c_str(),
+                    (unsigned long long)kv.second.first, kv.second.second);
+      js += item;
+      first = false;
+    }
+  }
+  js += "}";
+  if (js.size() + 1 > len) return fail(HT_EINVAL, "buffer too small");
+  std::memcpy(buf, js.c_str(), js.size() + 1);
+  return HT_OK;
+}
+
+int ht_probe_copy(const uint64_t* d_src, uint64_t* d_dst, uint64_t n, hipStream_t s) {
+  if (n == 0) return HT_OK;
+  if (!d_src || !d_dst) return fail(HT_EINVAL, "NULL pointer");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  HT_HIP(probe_copy(d_src, d_dst, n, device_cus(dev) * 8, s));
+  return HT_OK;
+}
+
+int ht_probe_gather(const uint64_t* d_array, uint64_t n_words, uint64_t n_access, uint32_t line_bytes,
+                    uint64_t seed, uint64_t* d_sink, hipStream_t s) {
+  if (n_access == 0) return HT_OK;
+  if (!d_array || !d_sink) return fail(HT_EINVAL, "NULL pointer");
+  if (line_bytes != 8 && line_bytes != 64 && line_bytes != 128) return fail(HT_EINVAL, "line_bytes must be 8, 64 or 128");
+  if (n_words < line_bytes / 8) return fail(HT_EINVAL, "array smaller than one line");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  HT_HIP(probe_gather(d_array, n_words, n_access, line_bytes, seed, d_sink, device_cus(dev) * 8, s));
+  return HT_OK;
+}
+
+int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access, uint64_t seed, hipStream_t s) {
+  if (n_access == 0) return HT_OK;
+  if (!d_array || n_words == 0) return fail(HT_EINVAL, "NULL or empty array");
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  HT_HIP(probe_cas(d_array, n_words, n_access, seed, device_cus(dev) * 8, s));
+  return HT_OK;
+}
+
+}  // extern "C"

@@ -113,7 +113,8 @@ def feistel_permutation(n: int, seed: int, idx: np.ndarray | None = None) -> np.
     """pi(idx) for a seeded pseudo-random bijection pi on [0, n).
 
     A balanced 4-round Feistel network on 2h bits (2^(2h) >= n) with
-    cycle-walking back into [0, n).  Returns uint64 indices.
+    cycle-walking back into [0, n); the round function is multiplicative
+    hashing of the right half xor a round key.  Returns uint64 indices.
     """
     if n <= 1:
         m = (n if idx is None else len(idx))
@@ -124,12 +125,16 @@ def feistel_permutation(n: int, seed: int, idx: np.ndarray | None = None) -> np.
     keys = [int(k) for k in splitmix64_stream(seed ^ 0x5F3759DF, 4)]
     x = np.arange(n, dtype=np.uint64) if idx is None else np.asarray(idx, dtype=np.uint64).copy()
 
+    # round function: top h bits of (right ^ k_r) * odd multiplier
+    mult = _u(0x9FB21C651E98DF25)
+    top = _U(64 - h)
+
     def rounds(v):
         left = v >> _U(h)
         right = v & mask
         for k in keys:
             with np.errstate(over="ignore"):
-                f = _sm_finalize(right ^ _u(k)) & mask
+                f = ((right ^ _u(k)) * mult) >> top
             left, right = right, left ^ f
         return (left << _U(h)) | right
 

@@ -1,0 +1,90 @@
+"""C ABI of libht.so on the CPU host: the library loads, exports every entry
+point include/ht.h declares, and rejects bad arguments before touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import pytest
+
+from paper_1712_09494_amd import binding as b
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_functions():
+    src = open(os.path.join(ROOT, "include", "ht.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(ht_[a-z_0-9]+)\s*\(", src)))
+
+
+def test_header_declares_expected_calls():
+    names = header_functions()
+    for must in ("ht_create", "ht_destroy", "ht_find_or_put", "ht_insert", "ht_query",
+                 "ht_find_or_put_multi", "ht_sync_status", "ht_rebuild", "ht_size", "ht_dump",
+                 "ht_dump_raw", "ht_clear", "ht_stats", "ht_strerror"):
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = b.load()
+    for name in header_functions():
+        assert hasattr(lib, name), name
+    assert set(header_functions()) == set(b.EXPORTED)
+
+
+def test_strerror_and_defaults():
+    lib = b.load()
+    for code in (b.HT_OK, b.HT_EINVAL, b.HT_ENOMEM, b.HT_EFULL, b.HT_EHIP):
+        assert lib.ht_strerror(code)
+    c = b.ht_config_default(b.HT_BUCKETED)
+    assert (c.kind, c.nhash, c.bucket_slots, c.stash_slots) == (b.HT_BUCKETED, 3, 16, 1024)
+    c = b.ht_config_default(b.HT_CUCKOO)
+    assert (c.kind, c.nhash, c.bucket_slots) == (b.HT_CUCKOO, 3, 0)
+
+
+@pytest.mark.parametrize("fn,args", [
+    ("ht_find_or_put", (None, None, 5, None, None)),
+    ("ht_query", (None, None, 5, None, None)),
+    ("ht_size", (None, None, None)),
+    ("ht_clear", (None, None)),
+    ("ht_destroy", (None,)),
+    ("ht_sync_status", (None, None)),
+    ("ht_reserve", (None, 10)),
+])
+def test_null_table_rejected(fn, args):
+    lib = b.load()
+    assert getattr(lib, fn)(*args) == b.HT_EINVAL
+    assert lib.ht_last_error()
+
+
+def test_bad_configs_rejected_without_gpu():
+    lib = b.load()
+    h = C.c_void_p()
+    bad = []
+    c = b.ht_config_default(b.HT_BUCKETED); c.capacity = 0; bad.append(c)
+    c = b.ht_config_default(b.HT_BUCKETED); c.capacity = 64; c.nhash = 0; bad.append(c)
+    c = b.ht_config_default(b.HT_BUCKETED); c.capacity = 64; c.nhash = 9; bad.append(c)
+    c = b.ht_config_default(b.HT_BUCKETED); c.capacity = 64; c.bucket_slots = 12; bad.append(c)
+    c = b.ht_config_default(b.HT_CUCKOO); c.capacity = 64; c.stash_slots = 100; bad.append(c)
+    c = b.ht_config_default(b.HT_CUCKOO); c.capacity = 64; c.flags = 1 << 9; bad.append(c)
+    c = b.ht_config_default(7); c.capacity = 64; bad.append(c)
+    for c in bad:
+        assert lib.ht_create(C.byref(c), C.byref(h)) == b.HT_EINVAL
+        assert h.value is None
+    assert lib.ht_find_or_put_multi(None, None, None, None, 3, None) == b.HT_EINVAL
+    assert lib.ht_find_or_put_multi(None, None, None, None, 0, None) == b.HT_OK
+    assert lib.ht_probe_gather(None, 0, 5, 64, 0, None, None) == b.HT_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    b2 = b.load  # the loader, pointed at a path with no library
+    import importlib
+    mod = importlib.import_module("paper_1712_09494_amd.binding")
+    saved = mod._lib
+    try:
+        mod._lib = None
+        with pytest.raises(b.HtLibraryMissing):
+            mod.load(str(tmp_path / "libht.so"))
+    finally:
+        mod._lib = saved
+    assert b2 is mod.load

@@ -3,9 +3,10 @@
 Workload (random-key scaling case): 2^26 uniform-random 64-bit keys with 10%
 duplicates (60,397,978 distinct), inserted by find-or-put in consecutive
 batches of 2^20 into a table sized for load factor 0.7.  One step = clear the
-table and find-or-put the whole sequence, for the bucketed table (B = 16,
-c = 3) and for the Cuckoo table (c = 3), i.e. 2 x 2^26 find-or-put operations.
-Keys are resident in HBM before the timed region starts.
+table and find-or-put the whole sequence, for the bucketed table (B = 8
+slots = 64-byte buckets, c = 3; the autotuner's pick for this shape) and for
+the Cuckoo table (c = 3), i.e. 2 x 2^26 find-or-put operations.  Keys are
+resident in HBM before the timed region starts.
 
 Printed as one JSON line: the headline value (whole-step find-or-put Mops/s),
 the roofline of the dominant kernel (HIP-event durations measured here, on
@@ -46,6 +47,11 @@ def parse():
     ap.add_argument("--no-sweep", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--designs", default="bucketed,cuckoo")
+    ap.add_argument("--bucket-slots", type=int, default=8)
+    ap.add_argument("--copy-calib", action="store_true",
+                    help="after the timed steps, copy 2^26 words once (counter calibration)")
+    ap.add_argument("--probes", action="store_true",
+                    help="only run the memory-system probes (copy, random gather, random CAS)")
     return ap.parse_args()
 
 
@@ -65,6 +71,9 @@ def main():
     torch.cuda.set_device(dev)
     b.load()
     stream = torch.cuda.current_stream()
+    if args.probes:
+        print(json.dumps({"probes": run_probes(b, torch, dev, stream)}), flush=True)
+        return
 
     t0 = time.time()
     seq, d = inputs.scaling_workload(n=args.n, dup_frac=args.dup, seed=inputs.SEED_BASE + 1)
@@ -77,7 +86,8 @@ def main():
     tables = {}
     for name in designs:
         if name == "bucketed":
-            tables[name] = b.Table("bucketed", capacity=cap, nhash=3, bucket_slots=16, max_batch=args.batch)
+            tables[name] = b.Table("bucketed", capacity=cap, nhash=3, bucket_slots=args.bucket_slots,
+                                   max_batch=args.batch)
         else:
             tables[name] = b.Table("cuckoo", capacity=cap, nhash=3, max_batch=args.batch)
 
@@ -104,6 +114,14 @@ def main():
     value = ops / elapsed / 1e6
     ms_per_step = elapsed / args.steps * 1e3
     log(f"[bench] timed {args.steps} steps: {ms_per_step:.2f} ms/step, {value:.1f} Mops/s")
+
+    if args.copy_calib:
+        # plain copy of known size: 512 MiB read + 512 MiB written
+        src = torch.zeros(1 << 26, dtype=torch.int64, device=dev)
+        dst = torch.empty_like(src)
+        b.ht_probe_copy(src, dst)
+        torch.cuda.synchronize()
+        del src, dst
 
     # correctness of the timed work (cheap invariants; full parity is in tests/)
     checks = {}
@@ -172,7 +190,7 @@ def main():
         "data": "synthetic",
         "config": {"workload": "random-key scaling: 2^26 uniform 64-bit keys, 10% duplicates, "
                                f"find-or-put in batches of {args.batch} at load factor {args.lf}; "
-                               "bucketed (B=16, c=3) + cuckoo (c=3) per step",
+                               f"bucketed (B={args.bucket_slots}, c=3) + cuckoo (c=3) per step",
                    "keys": args.n, "distinct": d, "batch": args.batch, "load_factor": args.lf,
                    "designs": designs},
         "roofline": rl,
@@ -187,31 +205,45 @@ def main():
     print(json.dumps(line), flush=True)
 
 
-# bytes each kernel must move per unit of work, for the roofline
-LINE = 64          # HBM access granularity assumed for a random 8-byte access
+# Algorithmic bytes per launch, for the roofline.  A random access moves one
+# 128-byte line from HBM (measured: random 8/64/128-byte gathers run at the
+# same line rate, and FETCH_SIZE shows 128 bytes per random 8-byte read); a
+# dirtied line writes back one 64-byte half (WRITE_SIZE per new key).
+LINE = 128
+HALF = 64
+
+
+def kernel_bytes(name, n, d_new, c, bucket_slots):
+    """Bytes a kernel must move for a batch of n keys of which d_new are new."""
+    if name == "bucketed_fop":
+        # key + flag + the first bucket's line(s); each new key dirties one half-line
+        lines = max(1, bucket_slots * 8 // LINE)
+        return n * (9 + LINE * lines) + d_new * HALF
+    if name == "cuckoo_probe":
+        # key + first slot line for keys found; all c slot lines + 16-byte list entry for misses;
+        # flag for hits
+        return n * 8 + (n - d_new) * (LINE + 1) + d_new * (c * LINE + 16)
+    if name == "cuckoo_place":
+        # list entry + compare-and-swap on one slot line (read + half-line write) + flag
+        return d_new * (16 + LINE + HALF + 1)
+    return None
 
 
 def roofline(per_kernel, args, d):
-    n = args.n
-    nb = (n + args.batch - 1) // args.batch
-    # algorithmic bytes per launch (one batch); see the kernel byte model
-    models = {
-        # key 8 B + flag 1 B + one 128 B bucket read per key; new keys write back one 64 B sector
-        "bucketed_fop": (9 + 128) * n / nb + LINE * d / nb,
-        # key + flag + first probed slot line per key; new keys: c-1 more probe lines + a 64 B scratch CAS
-        "cuckoo_probe": (9 + LINE) * n / nb + (2 * LINE + LINE) * d / nb,
-        # per winner: 16 B record + read-modify-write of one 64 B table line
-        "cuckoo_insert": (16 + 2 * LINE) * d / nb,
-    }
-    cands = {k: v for k, v in per_kernel.items() if k in models}
+    nb = (args.n + args.batch - 1) // args.batch
+    n = args.n / nb
+    d_new = d / nb
+    cands = {k: v for k, v in per_kernel.items()
+             if kernel_bytes(k, n, d_new, 3, args.bucket_slots) is not None}
     if not cands:
         return None
     dom = max(cands, key=lambda k: cands[k]["total_ms"])
-    bytes_per_launch = models[dom]
+    bytes_per_launch = kernel_bytes(dom, n, d_new, 3, args.bucket_slots)
     achieved = bytes_per_launch / (cands[dom]["avg_ms"] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
             "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-            "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": cands[dom]["avg_ms"]}
+            "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": cands[dom]["avg_ms"],
+            "keys_per_launch": int(n)}
 
 
 def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
@@ -225,7 +257,7 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
         for lf in (0.5, 0.7, 0.9):
             cap = int(np.ceil(d / lf))
             c = 4 if (kind == "cuckoo" and lf > 0.85) else 3
-            kw = dict(bucket_slots=16) if kind == "bucketed" else {}
+            kw = dict(bucket_slots=args.bucket_slots) if kind == "bucketed" else {}
             t = b.Table(kind, capacity=cap, nhash=c, max_batch=1 << 24, **kw)
             for batch in (1 << 16, 1 << 20, 1 << 24):
                 t.clear()
@@ -260,6 +292,45 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
                             "ok": hits == int(round(h * args.n))})
             t.close()
             log(f"[bench] sweep {kind} lf={lf} done")
+    return res
+
+
+def _timed(torch, stream, fn, reps=5):
+    fn()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        fn()
+    e1.record(stream)
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / reps * 1e-3
+
+
+def run_probes(b, torch, dev, stream):
+    """Memory-system reference rates: streaming copy, random line gathers and
+    random 64-bit CAS at working sets below and above the 256 MB MALL."""
+    res = {}
+    n = 1 << 28                                   # 2 GiB per buffer
+    src = torch.zeros(n, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    sec = _timed(torch, stream, lambda: b.ht_probe_copy(src, dst))
+    res["copy_GBps"] = round(2 * n * 8 / sec / 1e9, 1)
+    del dst
+    sink = torch.zeros(4, dtype=torch.int64, device=dev)
+    nacc = 1 << 26
+    for ws_mb in (16, 256, 2048):
+        words = ws_mb * (1 << 20) // 8
+        arr = src[:words]
+        for line in (8, 64, 128):
+            sec = _timed(torch, stream, lambda: b.ht_probe_gather(arr, nacc, line, 7, sink))
+            res[f"gather{line}_ws{ws_mb}MB_Gacc_s"] = round(nacc / sec / 1e9, 3)
+            res[f"gather{line}_ws{ws_mb}MB_GBps"] = round(nacc * line / sec / 1e9, 1)
+        sec = _timed(torch, stream, lambda: b.ht_probe_cas(arr, nacc, 9))
+        res[f"cas_ws{ws_mb}MB_Gops_s"] = round(nacc / sec / 1e9, 3)
+    del src
+    log(f"[bench] probes {res}")
     return res
 
 

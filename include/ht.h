@@ -96,7 +96,9 @@ typedef struct {
                               multiple of bucket_slots, cuckoo to a multiple of 16 */
   uint32_t bucket_slots;   /* bucketed: B in {8, 16, 32, 64}; 0 = 16 (one 128-byte
                               line of 64-bit keys).  Ignored by cuckoo */
-  uint32_t keys_per_group; /* work per lane group per step, 1 or 2; 0 = 1 */
+  uint32_t keys_per_group; /* keys each lane group (bucketed) or lane (cuckoo)
+                              keeps in flight: 1, 2 or 4; 0 = by design
+                              (bucketed B=8: 1, B=16: 2, B>=32: 4; cuckoo: 1) */
   uint32_t stash_slots;    /* stash size (power of two, <= 65536); 0 = 1024 */
   uint32_t max_chain;      /* cuckoo eviction bound; 0 = 8 * ceil(log2 capacity) */
   uint64_t seed;           /* seed of the hash constants */

@@ -38,7 +38,7 @@ def build(verbose: bool = False, extra: list[str] | None = None) -> str:
     tmp = LIB + ".tmp"
     cmd = [hipcc(), "-O3", "-std=c++17", f"--offload-arch={ARCH}", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
-           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
+           "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument", "-Wno-pass-failed",
            "-I", os.path.join(ROOT, "include"), "-I", CSRC,
            "-o", tmp] + sources() + (extra or [])
     if verbose:

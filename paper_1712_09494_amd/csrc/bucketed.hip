@@ -11,7 +11,10 @@
 // lanes, each loading 16 bytes, so one wave serves 128/B keys per step
 // (B = 16: a 128-byte line, 8 keys per wave).  Votes are 64-bit ballots cut
 // to the group's L bits; the compare-and-swap is issued by the lane that owns
-// the chosen slot and its result is broadcast to the group.
+// the chosen slot and its result is broadcast to the group.  Each group keeps
+// R keys in flight: every loop turn first issues the bucket loads of all R
+// keys, then evaluates them, then issues all their compare-and-swaps, then
+// resolves them, so the memory latencies of the R keys overlap.
 //
 // Placement protocol for one-word keys: a group always writes the lowest
 // slot that it sees empty.  Slots change only from empty to a key, so
@@ -33,149 +36,223 @@ namespace ht {
 template <int B>
 struct BucketGeo {
   static constexpr int L = B / 2;                                  // lanes per key
-  static constexpr int G = kWave / L;                              // keys per wave step
+  static constexpr int G = kWave / L;                              // key groups per wave
   static constexpr uint64_t GMASK = (L >= 64) ? ~0ull : ((1ull << L) - 1);
 };
 
-// Find-or-put of one key per lane group.  Called by all 64 lanes of a wave;
-// `k` and `active` are uniform within a group.  Returns 0/1/2 (see ht.h).
-template <int B, bool SCRIPTED, bool COHERENT>
-__device__ __forceinline__ uint32_t bucket_find_or_put(const DevTable& t, uint64_t k, bool active) {
-  using Geo = BucketGeo<B>;
-  constexpr int L = Geo::L;
+template <int B>
+__device__ __forceinline__ uint64_t group_bits(bool p, int g0) {
+  return (ballot(p) >> g0) & BucketGeo<B>::GMASK;
+}
+
+// Bucket number of position j of key k's probe sequence; `prev` is the bucket
+// of position j-1.
+template <bool SCRIPTED>
+__device__ __forceinline__ uint64_t probe_bucket(const DevTable& t, uint64_t k, uint32_t j, uint64_t prev) {
+  if (j < t.nhash) return hidx<SCRIPTED>(t, k, j);
+  return prev + 1 == t.nrange ? 0 : prev + 1;
+}
+
+// Find-or-put of R keys per lane group.  Called by all 64 lanes of a wave;
+// k[r] and active[r] are uniform within a group.  res[r] gets 0/1/2 (ht.h).
+template <int B, int R, bool SCRIPTED, bool COHERENT>
+__device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint64_t (&k)[R],
+                                                   const bool (&active)[R], uint32_t (&res)[R]) {
+  constexpr int L = BucketGeo<B>::L;
   const int lane = lane_id();
   const int gl = lane & (L - 1);
   const int g0 = lane - gl;                 // first lane of the group
-  uint32_t res = 0;
-  bool done = !active;
-  if (active && k == kEmpty) {
-    uint32_t won = 0;
-    if (gl == 0) won = sentinel_put(t);
-    res = shfl32(won, g0);
-    done = true;
+  const uint32_t nseq = t.nhash + t.walk;   // probe sequence length
+  bool done[R], need[R];
+  uint32_t j[R];
+  uint64_t b[R], v0[R], v1[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    res[r] = 0;
+    done[r] = !active[r];
+    need[r] = true;
+    j[r] = 0;
+    b[r] = 0;
+    v0[r] = v1[r] = kEmpty;
+    if (active[r] && k[r] == kEmpty) {     // all-ones key: flag word
+      uint32_t won = 0;
+      if (gl == 0) won = sentinel_put(t);
+      res[r] = shfl32(won, g0);
+      done[r] = true;
+    }
   }
-  uint32_t j = 0;                           // position in the probe sequence
-  uint64_t b = 0;                           // current bucket
-  uint64_t v0 = kEmpty, v1 = kEmpty;
-  uint64_t* bp = nullptr;
-  bool need_load = true;
-  while (ballot(!done)) {
-    if (!done) {
-      if (need_load) {
-        b = j < t.nhash ? hidx<SCRIPTED>(t, k, j) : (b + 1 == t.nrange ? 0 : b + 1);
-        bp = t.slots + b * (uint64_t)B;
-        load_pair<COHERENT>(bp + 2 * gl, v0, v1);
-        need_load = false;
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) any |= !done[r];
+    if (!ballot(any)) break;
+    // 1. issue the bucket loads
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!done[r] && need[r]) {
+        b[r] = probe_bucket<SCRIPTED>(t, k[r], j[r], b[r]);
+        load_pair<COHERENT>(t.slots + b[r] * (uint64_t)B + 2 * gl, v0[r], v1[r]);
+        need[r] = false;
       }
-      const uint64_t eq = (ballot((v0 == k) | (v1 == k)) >> g0) & Geo::GMASK;
-      if (eq) {
-        res = 0;
-        done = true;
-      } else {
-        const uint64_t e0 = (ballot(v0 == kEmpty) >> g0) & Geo::GMASK;
-        const uint64_t e1 = (ballot(v1 == kEmpty) >> g0) & Geo::GMASK;
-        const uint64_t ea = e0 | e1;
-        if (ea == 0) {
-          // bucket full: next bucket of the sequence, or the stash after it
-          if (++j < t.nhash + t.walk) {
-            need_load = true;
-          } else {
-            uint32_t r = 0;
-            if (gl == 0) r = stash_put(t, k);
-            res = shfl32(r, g0);
-            done = true;
-          }
+    }
+    // 2. vote: present / full / lowest empty slot
+    int tgt[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      tgt[r] = -1;
+      if (!done[r]) {
+        if (group_bits<B>((v0[r] == k[r]) | (v1[r] == k[r]), g0)) {
+          res[r] = 0;
+          done[r] = true;
         } else {
-          const int lf = __builtin_ctzll(ea);
-          const int which = ((e0 >> lf) & 1ull) ? 0 : 1;
-          uint64_t old = 0;
-          if (gl == lf) old = cas64(bp + 2 * lf + which, kEmpty, k);
-          old = shfl64(old, g0 + lf);
-          if (old == kEmpty) {
-            res = 1;
-            done = true;
-          } else if (old == k) {
-            res = 0;
-            done = true;
-          } else if (gl == lf) {
-            if (which == 0) v0 = old; else v1 = old;   // patch the stale copy
+          const uint64_t e0 = group_bits<B>(v0[r] == kEmpty, g0);
+          const uint64_t e1 = group_bits<B>(v1[r] == kEmpty, g0);
+          const uint64_t ea = e0 | e1;
+          if (ea == 0) {
+            if (++j[r] < nseq) {
+              need[r] = true;            // bucket full: next bucket of the sequence
+            } else {
+              uint32_t s = 0;
+              if (gl == 0) s = stash_put(t, k[r]);
+              res[r] = shfl32(s, g0);
+              done[r] = true;
+            }
+          } else {
+            const int lf = __builtin_ctzll(ea);
+            tgt[r] = 2 * lf + (((e0 >> lf) & 1ull) ? 0 : 1);
           }
         }
       }
     }
-  }
-  return res;
-}
-
-// Query of one key per lane group (read-only; runs after all writers).
-template <int B, bool SCRIPTED>
-__device__ __forceinline__ uint32_t bucket_query(const DevTable& t, uint64_t k, bool active,
-                                                 uint32_t stash_count, uint32_t overflow_count) {
-  using Geo = BucketGeo<B>;
-  constexpr int L = Geo::L;
-  const int lane = lane_id();
-  const int gl = lane & (L - 1);
-  const int g0 = lane - gl;
-  uint32_t res = 0;
-  bool done = !active;
-  if (active && k == kEmpty) {
-    res = t.ctr->sentinel ? 1u : 0u;
-    done = true;
-  }
-  uint32_t j = 0;
-  uint64_t b = 0;
-  while (ballot(!done)) {
-    if (!done) {
-      b = j < t.nhash ? hidx<SCRIPTED>(t, k, j) : (b + 1 == t.nrange ? 0 : b + 1);
-      uint64_t v0, v1;
-      load_pair<false>(t.slots + b * (uint64_t)B + 2 * gl, v0, v1);
-      const uint64_t eq = (ballot((v0 == k) | (v1 == k)) >> g0) & Geo::GMASK;
-      const uint64_t em = (ballot((v0 == kEmpty) | (v1 == kEmpty)) >> g0) & Geo::GMASK;
-      if (eq) {
-        res = 1;
-        done = true;
-      } else if (em) {
-        res = 0;            // first non-full bucket: the key would be here
-        done = true;
-      } else if (++j >= t.nhash + t.walk) {
-        uint32_t r = 0;
-        if (gl == 0) r = stash_query(t, k, stash_count, overflow_count) ? 1u : 0u;
-        res = shfl32(r, g0);
-        done = true;
+    // 3. issue the compare-and-swaps (lane owning the chosen slot)
+    uint64_t old[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      old[r] = 0;
+      if (tgt[r] >= 0 && gl == (tgt[r] >> 1))
+        old[r] = cas64(t.slots + b[r] * (uint64_t)B + tgt[r], kEmpty, k[r]);
+    }
+    // 4. resolve: won, found, or patch the stale copy and retry
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (tgt[r] >= 0) {
+        const int owner = tgt[r] >> 1;
+        const uint64_t o = shfl64(old[r], g0 + owner);
+        if (o == kEmpty) {
+          res[r] = 1;
+          done[r] = true;
+        } else if (o == k[r]) {
+          res[r] = 0;
+          done[r] = true;
+        } else if (gl == owner) {
+          if (tgt[r] & 1) v1[r] = o; else v0[r] = o;
+        }
       }
     }
   }
-  return res;
 }
 
-// Grid-stride find-or-put over n keys: each wave takes G keys per step.
-template <int B, bool SCRIPTED, bool COHERENT>
+// Query of R keys per lane group (read-only; runs after all writers).
+template <int B, int R, bool SCRIPTED>
+__device__ __forceinline__ void bucket_query(const DevTable& t, const uint64_t (&k)[R], const bool (&active)[R],
+                                             uint32_t stash_count, uint32_t overflow_count, uint32_t (&res)[R]) {
+  constexpr int L = BucketGeo<B>::L;
+  const int lane = lane_id();
+  const int gl = lane & (L - 1);
+  const int g0 = lane - gl;
+  const uint32_t nseq = t.nhash + t.walk;
+  bool done[R];
+  uint32_t j[R];
+  uint64_t b[R];
+#pragma unroll
+  for (int r = 0; r < R; ++r) {
+    res[r] = 0;
+    done[r] = !active[r];
+    j[r] = 0;
+    b[r] = 0;
+    if (active[r] && k[r] == kEmpty) {
+      res[r] = t.ctr->sentinel ? 1u : 0u;
+      done[r] = true;
+    }
+  }
+  for (;;) {
+    bool any = false;
+#pragma unroll
+    for (int r = 0; r < R; ++r) any |= !done[r];
+    if (!ballot(any)) break;
+    uint64_t v0[R], v1[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      v0[r] = v1[r] = kEmpty;
+      if (!done[r]) {
+        b[r] = probe_bucket<SCRIPTED>(t, k[r], j[r], b[r]);
+        load_pair<false>(t.slots + b[r] * (uint64_t)B + 2 * gl, v0[r], v1[r]);
+      }
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      if (!done[r]) {
+        const uint64_t eq = group_bits<B>((v0[r] == k[r]) | (v1[r] == k[r]), g0);
+        const uint64_t em = group_bits<B>((v0[r] == kEmpty) | (v1[r] == kEmpty), g0);
+        if (eq) {
+          res[r] = 1;
+          done[r] = true;
+        } else if (em) {
+          res[r] = 0;            // first non-full bucket: the key would be here
+          done[r] = true;
+        } else if (++j[r] >= nseq) {
+          uint32_t s = 0;
+          if (gl == 0) s = stash_query(t, k[r], stash_count, overflow_count) ? 1u : 0u;
+          res[r] = shfl32(s, g0);
+          done[r] = true;
+        }
+      }
+    }
+  }
+}
+
+// Grid-stride find-or-put: each wave step covers G*R keys; group g handles
+// keys base + r*G + g (consecutive groups read consecutive keys).
+template <int B, int R, bool SCRIPTED, bool COHERENT>
 __global__ __launch_bounds__(kBlock) void bucketed_fop_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                                uint64_t n, uint8_t* __restrict__ out) {
   using Geo = BucketGeo<B>;
+  constexpr uint64_t PER = (uint64_t)Geo::G * R;
   const int lane = lane_id();
   const int gl = lane & (Geo::L - 1);
   const int grp = lane / Geo::L;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   unsigned long long nnew = 0;
-  for (uint64_t base = wave * Geo::G; base < n; base += nwaves * Geo::G) {
-    const uint64_t i = base + grp;
-    const bool active = i < n;
-    const uint64_t k = active ? keys[i] : 0;
-    const uint32_t r = bucket_find_or_put<B, SCRIPTED, COHERENT>(t, k, active);
-    if (active && gl == 0) {
-      if (out) out[i] = (uint8_t)r;
-      nnew += (r == 1);
+  for (uint64_t base = wave * PER; base < n; base += nwaves * PER) {
+    uint64_t k[R];
+    bool act[R];
+    uint32_t res[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t i = base + (uint64_t)r * Geo::G + grp;
+      act[r] = i < n;
+      k[r] = act[r] ? keys[i] : 0;
+    }
+    bucket_find_or_put<B, R, SCRIPTED, COHERENT>(t, k, act, res);
+    if (gl == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (act[r]) {
+          if (out) out[base + (uint64_t)r * Geo::G + grp] = (uint8_t)res[r];
+          nnew += (res[r] == 1);
+        }
+      }
     }
   }
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
 }
 
-template <int B, bool SCRIPTED>
+template <int B, int R, bool SCRIPTED>
 __global__ __launch_bounds__(kBlock) void bucketed_query_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                                  uint64_t n, uint8_t* __restrict__ out) {
   using Geo = BucketGeo<B>;
+  constexpr uint64_t PER = (uint64_t)Geo::G * R;
   const int lane = lane_id();
   const int gl = lane & (Geo::L - 1);
   const int grp = lane / Geo::L;
@@ -183,64 +260,81 @@ __global__ __launch_bounds__(kBlock) void bucketed_query_kernel(DevTable t, cons
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   const uint32_t sc = t.ctr->stash_count;
   const uint32_t oc = t.ctr->overflow_count;
-  for (uint64_t base = wave * Geo::G; base < n; base += nwaves * Geo::G) {
-    const uint64_t i = base + grp;
-    const bool active = i < n;
-    const uint64_t k = active ? keys[i] : 0;
-    const uint32_t r = bucket_query<B, SCRIPTED>(t, k, active, sc, oc);
-    if (active && gl == 0) out[i] = (uint8_t)r;
+  for (uint64_t base = wave * PER; base < n; base += nwaves * PER) {
+    uint64_t k[R];
+    bool act[R];
+    uint32_t res[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const uint64_t i = base + (uint64_t)r * Geo::G + grp;
+      act[r] = i < n;
+      k[r] = act[r] ? keys[i] : 0;
+    }
+    bucket_query<B, R, SCRIPTED>(t, k, act, sc, oc, res);
+    if (gl == 0) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (act[r]) out[base + (uint64_t)r * Geo::G + grp] = (uint8_t)res[r];
+    }
   }
 }
 
 // ---- host launchers --------------------------------------------------------
 
-template <int B, bool S>
-static hipError_t launch_fop_b(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
-                               uint32_t grid, bool coherent, hipStream_t s) {
-  if (coherent)
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, S, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+template <int B, int R>
+static hipError_t launch_fop(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
+                             bool coherent, bool scripted, hipStream_t s) {
+  if (scripted)
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, 1, true, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+  else if (coherent)
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
   else
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, S, false>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, false>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
   return hipGetLastError();
 }
 
-template <int B, bool S>
-static hipError_t launch_query_b(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
-                                 uint32_t grid, hipStream_t s) {
-  hipLaunchKernelGGL((bucketed_query_kernel<B, S>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+template <int B, int R>
+static hipError_t launch_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
+                               bool scripted, hipStream_t s) {
+  if (scripted)
+    hipLaunchKernelGGL((bucketed_query_kernel<B, 1, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+  else
+    hipLaunchKernelGGL((bucketed_query_kernel<B, R, false>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
   return hipGetLastError();
 }
 
-uint64_t bucketed_keys_per_wave(uint32_t B) { return 128 / B; }
+// Keys one wave serves per loop turn.
+uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R) { return (128 / B) * R; }
+
+#define HT_BUCKET_DISPATCH(CALL)                                   \
+  switch (t.bucket_slots * 16 + R) {                               \
+    case 8 * 16 + 1: return CALL(8, 1);                            \
+    case 8 * 16 + 2: return CALL(8, 2);                            \
+    case 8 * 16 + 4: return CALL(8, 4);                            \
+    case 16 * 16 + 1: return CALL(16, 1);                          \
+    case 16 * 16 + 2: return CALL(16, 2);                          \
+    case 16 * 16 + 4: return CALL(16, 4);                          \
+    case 32 * 16 + 1: return CALL(32, 1);                          \
+    case 32 * 16 + 2: return CALL(32, 2);                          \
+    case 32 * 16 + 4: return CALL(32, 4);                          \
+    case 64 * 16 + 1: return CALL(64, 1);                          \
+    case 64 * 16 + 2: return CALL(64, 2);                          \
+    case 64 * 16 + 4: return CALL(64, 4);                          \
+    default: return hipErrorInvalidValue;                          \
+  }
 
 hipError_t bucketed_find_or_put(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
-                                uint32_t grid, bool coherent, bool scripted, hipStream_t s) {
-  switch (t.bucket_slots) {
-    case 8:  return scripted ? launch_fop_b<8, true>(t, keys, n, out, grid, coherent, s)
-                             : launch_fop_b<8, false>(t, keys, n, out, grid, coherent, s);
-    case 16: return scripted ? launch_fop_b<16, true>(t, keys, n, out, grid, coherent, s)
-                             : launch_fop_b<16, false>(t, keys, n, out, grid, coherent, s);
-    case 32: return scripted ? launch_fop_b<32, true>(t, keys, n, out, grid, coherent, s)
-                             : launch_fop_b<32, false>(t, keys, n, out, grid, coherent, s);
-    case 64: return scripted ? launch_fop_b<64, true>(t, keys, n, out, grid, coherent, s)
-                             : launch_fop_b<64, false>(t, keys, n, out, grid, coherent, s);
-    default: return hipErrorInvalidValue;
-  }
+                                uint32_t grid, uint32_t R, bool coherent, bool scripted, hipStream_t s) {
+#define HT_FOP(BB, RR) launch_fop<BB, RR>(t, keys, n, out, grid, coherent, scripted, s)
+  HT_BUCKET_DISPATCH(HT_FOP)
+#undef HT_FOP
 }
 
-hipError_t bucketed_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
-                          uint32_t grid, bool scripted, hipStream_t s) {
-  switch (t.bucket_slots) {
-    case 8:  return scripted ? launch_query_b<8, true>(t, keys, n, out, grid, s)
-                             : launch_query_b<8, false>(t, keys, n, out, grid, s);
-    case 16: return scripted ? launch_query_b<16, true>(t, keys, n, out, grid, s)
-                             : launch_query_b<16, false>(t, keys, n, out, grid, s);
-    case 32: return scripted ? launch_query_b<32, true>(t, keys, n, out, grid, s)
-                             : launch_query_b<32, false>(t, keys, n, out, grid, s);
-    case 64: return scripted ? launch_query_b<64, true>(t, keys, n, out, grid, s)
-                             : launch_query_b<64, false>(t, keys, n, out, grid, s);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t bucketed_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
+                          uint32_t R, bool scripted, hipStream_t s) {
+#define HT_QRY(BB, RR) launch_query<BB, RR>(t, keys, n, out, grid, scripted, s)
+  HT_BUCKET_DISPATCH(HT_QRY)
+#undef HT_QRY
 }
 
 }  // namespace ht

@@ -83,10 +83,11 @@ struct CuckooScratch {
   uint64_t* dset;        // deduplication set, dset_mask + 1 words, all empty between calls
   uint64_t dset_mask;
   uint64_t dset_seed;
-  uint64_t* wkey;        // winners: key
-  uint64_t* wmeta;       // winners: scratch-set slot | empty-candidate mask << 48
-  uint32_t* wcnt;        // winners per wave
-  uint64_t per_wave;     // keys (and winner room) per wave
+  uint64_t* wkey;        // listed keys, per-wave regions
+  uint64_t* wmeta;       // key index | empty-candidate mask << 48 (scratch-set slot after phase 3)
+  uint32_t* wcnt;        // misses per wave (phase 1)
+  uint32_t* ccnt;        // keys left for the eviction phase per wave (phase 2)
+  uint64_t per_wave;     // keys (and list room) per wave
 };
 
 template <bool SCRIPTED>

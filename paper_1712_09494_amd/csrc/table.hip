@@ -14,14 +14,20 @@
 
 namespace ht {
 // kernels (bucketed.hip, cuckoo.hip, util.hip, multi.hip)
-hipError_t bucketed_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, bool,
-                                hipStream_t);
-hipError_t bucketed_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
-uint64_t bucketed_keys_per_wave(uint32_t B);
-hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
+hipError_t bucketed_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
+                                bool, hipStream_t);
+hipError_t bucketed_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
+                          hipStream_t);
+uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R);
+hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
+                        hipStream_t);
 hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
-                        bool, hipStream_t);
-hipError_t cuckoo_insert(const DevTable&, uint64_t, const CuckooScratch&, uint32_t, bool, bool, hipStream_t);
+                        uint32_t, bool, hipStream_t);
+hipError_t cuckoo_place(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t, bool,
+                        hipStream_t);
+hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, bool,
+                        hipStream_t);
+hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, bool, hipStream_t);
 hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
@@ -239,7 +245,7 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   const uint64_t nw = (uint64_t)max_blocks(t) * (kBlock / kWave);
   const size_t b_dset = align_up(ds * 8, 256);
   const size_t b_k = align_up(n * 8, 256);
-  const size_t b_c = align_up(nw * 4, 256);
+  const size_t b_c = align_up(2 * nw * 4, 256);   // wcnt and ccnt
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c);
   if (e != hipSuccess) {
@@ -272,7 +278,8 @@ int validate_config(const ht_config* c) {
   if (c->stash_slots && (c->stash_slots & (c->stash_slots - 1)))
     return fail(HT_EINVAL, "stash_slots must be a power of two");
   if (c->stash_slots > 65536) return fail(HT_EINVAL, "stash_slots above 65536");
-  if (c->keys_per_group > 2) return fail(HT_EINVAL, "keys_per_group must be 0, 1 or 2");
+  if (c->keys_per_group != 0 && c->keys_per_group != 1 && c->keys_per_group != 2 && c->keys_per_group != 4)
+    return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL))
     return fail(HT_EINVAL, "unknown flag bits");
@@ -296,7 +303,11 @@ void setup_geometry(ht_table* t) {
   if (!c.stash_slots) c.stash_slots = 1024;
   if (!c.overflow_slots) c.overflow_slots = 65536;
   if (!c.max_chain) c.max_chain = 8 * std::max<uint32_t>(1, ceil_log2(t->nslots));
-  if (!c.keys_per_group) c.keys_per_group = 1;
+  if (!c.keys_per_group) {
+    // measured best per bucket width (B = 8: 16 keys per wave already)
+    if (c.kind == HT_CUCKOO) c.keys_per_group = 1;
+    else c.keys_per_group = c.bucket_slots <= 8 ? 1 : (c.bucket_slots == 16 ? 2 : 4);
+  }
   t->dev.nhash = c.nhash;
   t->dev.bucket_slots = c.bucket_slots;
   t->dev.stash_slots = c.stash_slots;
@@ -350,18 +361,19 @@ DevTable launch_view(const ht_table* t) {
 int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
+  const uint32_t R = t->cfg.keys_per_group;
   if (t->cfg.kind == HT_BUCKETED) {
-    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots);
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R);
     const uint64_t waves = (n + g - 1) / g;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_fop", s);
-    HT_HIP(bucketed_find_or_put(d, keys, n, out, (uint32_t)blocks,
+    HT_HIP(bucketed_find_or_put(d, keys, n, out, (uint32_t)blocks, R,
                                 (t->cfg.flags & HT_FLAG_CACHED_LOADS) == 0, scripted, s));
     return HT_OK;
   }
   int rc = reserve_scratch(t, n);
   if (rc != HT_OK) return rc;
-  const uint64_t waves_needed = (n + kWave - 1) / kWave;
+  const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
   const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
   const uint64_t nwaves = blocks * 4;
   CuckooScratch sc;
@@ -371,14 +383,24 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
   sc.wkey = t->wkey;
   sc.wmeta = t->wmeta;
   sc.wcnt = t->wcnt;
+  sc.ccnt = t->wcnt + (uint64_t)max_blocks(t) * (kBlock / kWave);
   sc.per_wave = (n + nwaves - 1) / nwaves;
   {
     KernelTimer kt("cuckoo_probe", s);
-    HT_HIP(cuckoo_probe(d, keys, n, out, sc, (uint32_t)blocks, scripted, s));
+    HT_HIP(cuckoo_probe(d, keys, n, out, sc, (uint32_t)blocks, R, scripted, s));
+  }
+  const bool paper = (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
+  if (!paper) {
+    KernelTimer kt("cuckoo_place", s);
+    HT_HIP(cuckoo_place(d, n, out, sc, (uint32_t)blocks, R, scripted, s));
   }
   {
-    KernelTimer kt("cuckoo_insert", s);
-    HT_HIP(cuckoo_insert(d, n, sc, (uint32_t)blocks, scripted, (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0, s));
+    KernelTimer kt("cuckoo_evict", s);
+    HT_HIP(cuckoo_evict(d, n, out, sc, (uint32_t)blocks, scripted, paper, s));
+  }
+  {
+    KernelTimer kt("cuckoo_scrub", s);
+    HT_HIP(cuckoo_scrub(n, sc, (uint32_t)blocks, paper, s));
   }
   return HT_OK;
 }
@@ -386,16 +408,18 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
 int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
+  const uint32_t R = t->cfg.keys_per_group;
   if (t->cfg.kind == HT_BUCKETED) {
-    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots);
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R);
     const uint64_t waves = (n + g - 1) / g;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_query", s);
-    HT_HIP(bucketed_query(d, keys, n, out, (uint32_t)blocks, scripted, s));
+    HT_HIP(bucketed_query(d, keys, n, out, (uint32_t)blocks, R, scripted, s));
   } else {
-    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    const uint64_t per = (uint64_t)kBlock * R;
+    const uint64_t blocks = std::min<uint64_t>((n + per - 1) / per, max_blocks(t));
     KernelTimer kt("cuckoo_query", s);
-    HT_HIP(cuckoo_query(d, keys, n, out, (uint32_t)blocks, scripted, s));
+    HT_HIP(cuckoo_query(d, keys, n, out, (uint32_t)blocks, R, scripted, s));
   }
   return HT_OK;
 }
@@ -440,7 +464,7 @@ void ht_config_default(ht_config* cfg, uint32_t kind) {
   cfg->kind = kind;
   cfg->nhash = 3;
   cfg->bucket_slots = kind == HT_BUCKETED ? 16 : 0;
-  cfg->keys_per_group = 1;
+  cfg->keys_per_group = 0;
   cfg->stash_slots = 1024;
   cfg->overflow_slots = 65536;
   cfg->bucket_walk = kind == HT_BUCKETED ? 64 : 0;

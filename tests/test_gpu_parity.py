@@ -23,8 +23,15 @@ DESIGNS = {
     "bkt16_cached": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_CACHED_LOADS),
     "cuckoo": dict(kind="cuckoo"),
     "cuckoo_paper": dict(kind="cuckoo", flags=b.HT_FLAG_CUCKOO_PAPER_ORDER),
+    "bkt16_r1": dict(kind="bucketed", bucket_slots=16, keys_per_group=1),
+    "bkt8_r4": dict(kind="bucketed", bucket_slots=8, keys_per_group=4),
+    "bkt64_r4": dict(kind="bucketed", bucket_slots=64, keys_per_group=4),
+    "cuckoo_r1": dict(kind="cuckoo", keys_per_group=1),
+    "cuckoo_r4": dict(kind="cuckoo", keys_per_group=4),
+    "bkt16_paperfull": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL),
 }
 MAIN = ["bkt16", "bkt8", "bkt16_cached", "cuckoo", "cuckoo_paper"]
+MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4"]
 
 
 def dev(a):
@@ -116,7 +123,7 @@ def test_random_small_tables(design):
         t.close()
 
 
-@pytest.mark.parametrize("design", MAIN + ["bkt32", "bkt64"])
+@pytest.mark.parametrize("design", MAIN + MORE + ["bkt32", "bkt64", "bkt64_r4"])
 def test_small_workload_2p20(design):
     """2^20 distinct keys at load factor 0.5, then 2^20 queries half present."""
     ins, q = inputs.small_workload()
@@ -157,7 +164,7 @@ def test_random_scaling_batches(design, lf, batch):
     t.close()
 
 
-@pytest.mark.parametrize("design", MAIN)
+@pytest.mark.parametrize("design", MAIN + MORE)
 def test_bfs_levels(design):
     """Synthetic 16-process BFS, levels 0..4: one find-or-put batch per level."""
     model = inputs.BfsModel(1)
@@ -176,7 +183,7 @@ def test_bfs_levels(design):
     t.close()
 
 
-@pytest.mark.parametrize("design", MAIN)
+@pytest.mark.parametrize("design", MAIN + MORE)
 def test_duplicate_storms(design):
     t = make(design, 1 << 16)
     # one key 2^20 times

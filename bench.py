@@ -229,6 +229,35 @@ def kernel_bytes(name, n, d_new, c, bucket_slots):
     return None
 
 
+def kernel_source_hash() -> str:
+    """sha256 over the HIP sources, to tell whether committed counters are current."""
+    import glob
+    import hashlib
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1712_09494_amd", "csrc")
+    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
+        h.update(os.path.basename(p).encode())
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def measured_traffic(kernel: str, workload: str = "random_scaling_2p26"):
+    """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
+    summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
+    or None when the summary is missing or the kernels changed since."""
+    p = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    try:
+        with open(p) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel + "_kernel") or c.get("kernels", {}).get(kernel)
+    return None if k is None else int(k["bytes_scaled"])
+
+
 def roofline(per_kernel, args, d):
     nb = (args.n + args.batch - 1) // args.batch
     n = args.n / nb
@@ -241,7 +270,8 @@ def roofline(per_kernel, args, d):
     bytes_per_launch = kernel_bytes(dom, n, d_new, 3, args.bucket_slots)
     achieved = bytes_per_launch / (cands[dom]["avg_ms"] * 1e-3) / 1e9
     return {"kernel": dom, "bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": measured_traffic(dom) if (args.batch == 1 << 20 and args.n == 1 << 26) else None,
             "bytes_per_launch": int(bytes_per_launch), "avg_launch_ms": cands[dom]["avg_ms"],
             "keys_per_launch": int(n)}
 
@@ -336,7 +366,7 @@ def run_probes(b, torch, dev, stream):
 
 def cpu_baseline(seq, batch):
     from oracle import Oracle
-    sample = min(seq.size, 1 << 23)
+    sample = min(seq.size, 1 << 25)
     o = Oracle()
     t0 = time.perf_counter()
     for s0 in range(0, sample, batch):

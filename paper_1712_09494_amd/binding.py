@@ -131,6 +131,12 @@ def load(path: str = LIB_PATH) -> C.CDLL:
     if not os.path.exists(path):
         raise HtLibraryMissing(
             f"{path} is not built; run `python -m paper_1712_09494_amd.build` (hipcc, gfx950)")
+    try:
+        # load torch's HIP runtime first so that libht.so binds to the same one
+        # (one runtime per process: torch's stream handles are then valid here)
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = C.CDLL(path)
     for name, (res, args) in _PROTOS.items():
         f = getattr(lib, name)

@@ -50,6 +50,9 @@ def parse():
     ap.add_argument("--bucket-slots", type=int, default=8)
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the timed steps, copy 2^26 words once (counter calibration)")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batched-only", action="store_true",
+                    help="only run the many-table (batched) measurement")
     ap.add_argument("--probes", action="store_true",
                     help="only run the memory-system probes (copy, random gather, random CAS)")
     return ap.parse_args()
@@ -73,6 +76,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.probes:
         print(json.dumps({"probes": run_probes(b, torch, dev, stream)}), flush=True)
+        return
+    if args.batched_only:
+        print(json.dumps({"batched": run_batched(b, inputs, torch, dev, stream)}), flush=True)
         return
 
     t0 = time.time()
@@ -171,6 +177,10 @@ def main():
     if not args.no_sweep:
         sweep = run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out)
 
+    batched = None
+    if not args.no_batched:
+        batched = run_batched(b, inputs, torch, dev, stream)
+
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(seq, args.batch)
@@ -199,6 +209,7 @@ def main():
         "per_kernel": per_kernel,
         "checks": checks,
         "sweep": sweep,
+        "batched": batched,
     }
     for t in tables.values():
         t.close()
@@ -361,6 +372,118 @@ def run_probes(b, torch, dev, stream):
         res[f"cas_ws{ws_mb}MB_Gops_s"] = round(nacc / sec / 1e9, 3)
     del src
     log(f"[bench] probes {res}")
+    return res
+
+
+def batched_workload(inputs, ntables=256, lf=0.6):
+    """256 tables with capacities log-uniform in [2^10, 2^22), each with
+    floor(lf * cap) distinct keys: even tables random keys, odd tables a
+    prefix of one synthetic BFS successor stream (16-process model, seed 1,
+    levels 0-4) holding that many distinct keys (duplicates included; the
+    stream holds 2,049,037 distinct states, which caps the largest BFS
+    tables)."""
+    from paper_1712_09494_amd.inputs import SplitMix64, BfsModel
+    r = SplitMix64(0x1712094940 + 3)
+    caps = []
+    for _ in range(ntables):
+        u = 10 + 12 * (r.next() / 2.0 ** 64)
+        caps.append(int(round(2 ** u)))
+    model = BfsModel(1)
+    frontier = np.array([0], dtype=np.uint64)
+    parts = []
+    seen = np.array([0], dtype=np.uint64)
+    for _ in range(5):
+        batch = model.successors(frontier)
+        parts.append(batch)
+        u, first = np.unique(batch, return_index=True)
+        new = ~np.isin(u, seen)
+        frontier = batch[np.sort(first[new])]
+        seen = np.union1d(seen, u[new])
+    stream = np.concatenate(parts)
+    _, first = np.unique(stream, return_index=True)
+    first = np.sort(first)
+    keys, distinct = [], []
+    for t, cap in enumerate(caps):
+        d = max(1, int(lf * cap))
+        if t % 2 == 0:
+            keys.append(inputs.uniform_keys(d, seed=0x1712094940 + 4 + t))
+        else:
+            d = min(d, first.size)
+            keys.append(stream[: int(first[d - 1]) + 1])
+        distinct.append(d)
+    return caps, keys, distinct
+
+
+def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
+    """Many tables: 256 plain per-table calls vs one persistent launch (plan)
+    vs the plan's launch replayed from a captured HIP graph."""
+    from paper_1712_09494_amd import tune
+    t0 = time.time()
+    caps, keys, distinct = batched_workload(inputs, ntables, lf)
+    kd = [torch.from_numpy(k.view(np.int64)).to(dev) for k in keys]
+    outs = [torch.empty(k.numel(), dtype=torch.uint8, device=dev) for k in kd]
+    total = int(sum(k.numel() for k in kd))
+    log(f"[bench] batched workload: {ntables} tables, {total} keys ({time.time() - t0:.1f}s)")
+    res = {"tables": ntables, "keys": total, "load_factor": lf,
+           "capacity_total": int(sum(caps)), "designs": {}}
+    for kind in ("bucketed", "cuckoo"):
+        # autotuned parameters per size class (log2 capacity), cached in-process
+        tuned = {}
+        for cap in caps:
+            key = tune.cache_key(kind, cap, lf)
+            if key not in tuned:
+                grid = ([dict(bucket_slots=B, nhash=c, keys_per_group=1) for B in (8, 16, 32, 64) for c in (2, 3)]
+                        if kind == "bucketed" else [dict(nhash=c, keys_per_group=1) for c in (3, 4)])
+                tuned[key] = tune.tune(kind, 1 << int(np.log2(cap)), lf, grid=grid, reps=2,
+                                       cache_path=None)["best"]
+        tables = [b.Table(kind, capacity=cap, max_batch=k.numel(), **tuned[tune.cache_key(kind, cap, lf)])
+                  for cap, k in zip(caps, kd)]
+
+        def clear_all():
+            for t in tables:
+                t.clear()
+            torch.cuda.synchronize()
+
+        def timed(fn):
+            best = None
+            for _ in range(reps):
+                clear_all()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn()
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+                best = ms if best is None else min(best, ms)
+            return best
+
+        plain_ms = timed(lambda: [t.find_or_put(k, o) for t, k, o in zip(tables, kd, outs)])
+        ok_plain = all(t.size() == d for t, d in zip(tables, distinct))
+        plan = b.MultiPlan(tables, kd, outs)
+        plan_ms = timed(lambda: plan.launch())
+        ok_plan = plan.status() == b.HT_OK and all(t.size() == d for t, d in zip(tables, distinct))
+        g = torch.cuda.CUDAGraph()
+        s = torch.cuda.Stream()
+        s.wait_stream(torch.cuda.current_stream())
+        clear_all()
+        with torch.cuda.stream(s):
+            with torch.cuda.graph(g, stream=s):
+                plan.launch()
+        torch.cuda.synchronize()
+        graph_ms = timed(lambda: g.replay())
+        ok_graph = plan.status() == b.HT_OK and all(t.size() == d for t, d in zip(tables, distinct))
+        res["designs"][kind] = {
+            "plain_ms": round(plain_ms, 3), "plan_ms": round(plan_ms, 3), "graph_ms": round(graph_ms, 3),
+            "plain_mops": round(total / plain_ms / 1e3, 1), "graph_mops": round(total / graph_ms / 1e3, 1),
+            "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
+            "tuned_classes": {k: v for k, v in sorted(tuned.items())},
+            "ok": bool(ok_plain and ok_plan and ok_graph)}
+        log(f"[bench] batched {kind}: plain {plain_ms:.2f} ms, plan {plan_ms:.2f} ms, graph {graph_ms:.2f} ms")
+        del g
+        plan.close()
+        for t in tables:
+            t.close()
     return res
 
 

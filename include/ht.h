@@ -155,15 +155,41 @@ int ht_insert(ht_table* t, const uint64_t* d_keys, uint64_t n,
 int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n,
              uint8_t* d_out_found, hipStream_t stream);
 
-/* Find-or-put into `ntables` tables in one persistent launch (the many-table
- * form of Sec. 5's find-or-insert kernel).  t[i], d_keys[i], n[i],
+/* Find-or-put into `ntables` tables at once (the find-or-insert benchmark
+ * kernel of Sec. 5, applied to many tables).  t[i], d_keys[i], n[i],
  * d_out_is_new[i] are host arrays of per-table arguments (the key and flag
- * pointers themselves are device pointers).  Tables may mix kinds, bucket
- * sizes and hash counts; each table must appear at most once.  Results equal
- * one ht_find_or_put per table. */
+ * pointers themselves are device pointers; a flag pointer may be NULL).
+ * Tables may mix kinds, bucket sizes and hash counts; each table may appear
+ * at most once; scripted-hash tables are rejected.  All bucketed tables are
+ * served by one persistent kernel; each Cuckoo table then runs its own phase
+ * kernels on the same stream.  Results equal one ht_find_or_put per table.
+ * Builds a plan (allocating), launches it and synchronises `stream`. */
 int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
                          uint32_t ntables, hipStream_t stream);
+
+typedef struct ht_multi_plan ht_multi_plan;
+
+/* Prepare a many-table find-or-put: validates the arguments, reserves each
+ * Cuckoo table's scratch for its batch, and copies the bucketed tables'
+ * descriptors and work queue to the device (allocates, synchronises).  The
+ * key and flag buffers must stay valid for every launch of the plan. */
+int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
+                         const uint64_t* n, uint8_t* const* d_out_is_new,
+                         uint32_t ntables, ht_multi_plan** out);
+
+/* Run the plan on `stream`: a small reset kernel and one persistent kernel
+ * for the bucketed tables, then the phase kernels of each Cuckoo table.
+ * Allocates nothing, uses no memset and does not synchronise, so it may be
+ * captured in a HIP graph and replayed.  Launches of one plan, and calls on
+ * its tables, must be ordered on one stream. */
+int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t stream);
+
+/* Synchronises `stream`; HT_EHIP if it reports an error, else HT_OK. */
+int ht_multi_plan_status(ht_multi_plan* p, hipStream_t stream);
+
+/* Free the plan's device memory (synchronises the device). */
+int ht_multi_plan_destroy(ht_multi_plan* p);
 
 /* Synchronises `stream`; HT_EFULL if keys went to the overflow list (or were
  * lost) since the table was created or last rebuilt, else HT_OK. */

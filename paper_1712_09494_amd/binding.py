@@ -99,6 +99,11 @@ _PROTOS = {
     "ht_insert": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_query": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_find_or_put_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
+    "ht_multi_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32,
+                                       C.POINTER(_vp)]),
+    "ht_multi_plan_launch": (C.c_int, [_vp, _vp]),
+    "ht_multi_plan_status": (C.c_int, [_vp, _vp]),
+    "ht_multi_plan_destroy": (C.c_int, [_vp]),
     "ht_sync_status": (C.c_int, [_vp, _vp]),
     "ht_rebuild": (C.c_int, [_vp, _u64, _vp]),
     "ht_size": (C.c_int, [_vp, C.POINTER(_u64), _vp]),
@@ -259,6 +264,45 @@ def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=No
     op = (_vp * n)(*[o.data_ptr() for o in os_])
     _check(load().ht_find_or_put_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_find_or_put_multi")
     return os_
+
+
+class MultiPlan:
+    """A prepared many-table find-or-put (ht_multi_plan_*).  The key and
+    flag tensors are kept alive by the plan; launch() allocates nothing and
+    may run inside torch.cuda.graph capture."""
+
+    def __init__(self, tables, keys_list, outs=None):
+        n = len(tables)
+        self.tables = list(tables)
+        self.keys = [_key_tensor(k) for k in keys_list]
+        if len(self.keys) != n:
+            raise ValueError("one key tensor per table")
+        self.outs = [_out_tensor(None if outs is None else outs[i], self.keys[i].numel(), self.keys[i])
+                     for i in range(n)]
+        th = (_vp * n)(*[t.handle for t in self.tables])
+        kp = (_vp * n)(*[k.data_ptr() for k in self.keys])
+        nn = (_u64 * n)(*[k.numel() for k in self.keys])
+        op = (_vp * n)(*[o.data_ptr() for o in self.outs])
+        h = _vp()
+        _check(load().ht_multi_plan_create(th, kp, nn, op, n, C.byref(h)), "ht_multi_plan_create")
+        self.handle = h.value
+
+    def launch(self, stream=None):
+        _check(load().ht_multi_plan_launch(self.handle, _stream_handle(stream)), "ht_multi_plan_launch")
+
+    def status(self, stream=None) -> int:
+        return load().ht_multi_plan_status(self.handle, _stream_handle(stream))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().ht_multi_plan_destroy(self.handle), "ht_multi_plan_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def ht_sync_status(h: int, stream=None) -> int:

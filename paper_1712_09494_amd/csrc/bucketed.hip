@@ -1,283 +1,7 @@
-// Bucketed (GPUexplore-style) table: find-or-put and query kernels.
-//
-// Paper Sec. 4.2 / Fig. 4: a key is hashed with h_1 to a bucket; the whole
-// bucket is read cooperatively, one slot share per lane; the lanes vote
-// whether the key is already there and which slots are free; a free slot is
-// written atomically; a lost race moves on to the next free slot; a full
-// bucket moves on to h_2, ...; when all c buckets are full the table is full.
-// Sec. 5.1.2 reduces the element to one word per key, as here.
-//
-// wave64 layout: a bucket of B 64-bit slots is read by a group of L = B/2
-// lanes, each loading 16 bytes, so one wave serves 128/B keys per step
-// (B = 16: a 128-byte line, 8 keys per wave).  Votes are 64-bit ballots cut
-// to the group's L bits; the compare-and-swap is issued by the lane that owns
-// the chosen slot and its result is broadcast to the group.  Each group keeps
-// R keys in flight: every loop turn first issues the bucket loads of all R
-// keys, then evaluates them, then issues all their compare-and-swaps, then
-// resolves them, so the memory latencies of the R keys overlap.
-//
-// Placement protocol for one-word keys: a group always writes the lowest
-// slot that it sees empty.  Slots change only from empty to a key, so
-// occupied slots of a bucket form a prefix, a bucket seen full stays full,
-// and two inserters of the same key walk the same buckets and meet at the
-// same slot.  A stale empty slot is fixed by the compare-and-swap result (the
-// group patches its copy and moves on), so no reload is needed.  A query may
-// stop at the first bucket that is not full.
-//
-// Probe sequence: the buckets of h_1..h_c, then (unless the table keeps the
-// paper's "full after c buckets" rule) up to `walk` consecutive buckets after
-// h_c's bucket, then the stash.  The sequence depends only on the key, so the
-// invariants above hold along it.  With c = 3 and B = 16 the c buckets alone
-// reject about 0.7% of keys at load factor 0.9; the walk takes them.
-#include "ht_device.h"
+// Host launchers of the bucketed-table kernels (device code: bucketed_dev.h).
+#include "bucketed_dev.h"
 
 namespace ht {
-
-template <int B>
-struct BucketGeo {
-  static constexpr int L = B / 2;                                  // lanes per key
-  static constexpr int G = kWave / L;                              // key groups per wave
-  static constexpr uint64_t GMASK = (L >= 64) ? ~0ull : ((1ull << L) - 1);
-};
-
-template <int B>
-__device__ __forceinline__ uint64_t group_bits(bool p, int g0) {
-  return (ballot(p) >> g0) & BucketGeo<B>::GMASK;
-}
-
-// Bucket number of position j of key k's probe sequence; `prev` is the bucket
-// of position j-1.
-template <bool SCRIPTED>
-__device__ __forceinline__ uint64_t probe_bucket(const DevTable& t, uint64_t k, uint32_t j, uint64_t prev) {
-  if (j < t.nhash) return hidx<SCRIPTED>(t, k, j);
-  return prev + 1 == t.nrange ? 0 : prev + 1;
-}
-
-// Find-or-put of R keys per lane group.  Called by all 64 lanes of a wave;
-// k[r] and active[r] are uniform within a group.  res[r] gets 0/1/2 (ht.h).
-template <int B, int R, bool SCRIPTED, bool COHERENT>
-__device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint64_t (&k)[R],
-                                                   const bool (&active)[R], uint32_t (&res)[R]) {
-  constexpr int L = BucketGeo<B>::L;
-  const int lane = lane_id();
-  const int gl = lane & (L - 1);
-  const int g0 = lane - gl;                 // first lane of the group
-  const uint32_t nseq = t.nhash + t.walk;   // probe sequence length
-  bool done[R], need[R];
-  uint32_t j[R];
-  uint64_t b[R], v0[R], v1[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    res[r] = 0;
-    done[r] = !active[r];
-    need[r] = true;
-    j[r] = 0;
-    b[r] = 0;
-    v0[r] = v1[r] = kEmpty;
-    if (active[r] && k[r] == kEmpty) {     // all-ones key: flag word
-      uint32_t won = 0;
-      if (gl == 0) won = sentinel_put(t);
-      res[r] = shfl32(won, g0);
-      done[r] = true;
-    }
-  }
-  for (;;) {
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) any |= !done[r];
-    if (!ballot(any)) break;
-    // 1. issue the bucket loads
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (!done[r] && need[r]) {
-        b[r] = probe_bucket<SCRIPTED>(t, k[r], j[r], b[r]);
-        load_pair<COHERENT>(t.slots + b[r] * (uint64_t)B + 2 * gl, v0[r], v1[r]);
-        need[r] = false;
-      }
-    }
-    // 2. vote: present / full / lowest empty slot
-    int tgt[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      tgt[r] = -1;
-      if (!done[r]) {
-        if (group_bits<B>((v0[r] == k[r]) | (v1[r] == k[r]), g0)) {
-          res[r] = 0;
-          done[r] = true;
-        } else {
-          const uint64_t e0 = group_bits<B>(v0[r] == kEmpty, g0);
-          const uint64_t e1 = group_bits<B>(v1[r] == kEmpty, g0);
-          const uint64_t ea = e0 | e1;
-          if (ea == 0) {
-            if (++j[r] < nseq) {
-              need[r] = true;            // bucket full: next bucket of the sequence
-            } else {
-              uint32_t s = 0;
-              if (gl == 0) s = stash_put(t, k[r]);
-              res[r] = shfl32(s, g0);
-              done[r] = true;
-            }
-          } else {
-            const int lf = __builtin_ctzll(ea);
-            tgt[r] = 2 * lf + (((e0 >> lf) & 1ull) ? 0 : 1);
-          }
-        }
-      }
-    }
-    // 3. issue the compare-and-swaps (lane owning the chosen slot)
-    uint64_t old[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      old[r] = 0;
-      if (tgt[r] >= 0 && gl == (tgt[r] >> 1))
-        old[r] = cas64(t.slots + b[r] * (uint64_t)B + tgt[r], kEmpty, k[r]);
-    }
-    // 4. resolve: won, found, or patch the stale copy and retry
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (tgt[r] >= 0) {
-        const int owner = tgt[r] >> 1;
-        const uint64_t o = shfl64(old[r], g0 + owner);
-        if (o == kEmpty) {
-          res[r] = 1;
-          done[r] = true;
-        } else if (o == k[r]) {
-          res[r] = 0;
-          done[r] = true;
-        } else if (gl == owner) {
-          if (tgt[r] & 1) v1[r] = o; else v0[r] = o;
-        }
-      }
-    }
-  }
-}
-
-// Query of R keys per lane group (read-only; runs after all writers).
-template <int B, int R, bool SCRIPTED>
-__device__ __forceinline__ void bucket_query(const DevTable& t, const uint64_t (&k)[R], const bool (&active)[R],
-                                             uint32_t stash_count, uint32_t overflow_count, uint32_t (&res)[R]) {
-  constexpr int L = BucketGeo<B>::L;
-  const int lane = lane_id();
-  const int gl = lane & (L - 1);
-  const int g0 = lane - gl;
-  const uint32_t nseq = t.nhash + t.walk;
-  bool done[R];
-  uint32_t j[R];
-  uint64_t b[R];
-#pragma unroll
-  for (int r = 0; r < R; ++r) {
-    res[r] = 0;
-    done[r] = !active[r];
-    j[r] = 0;
-    b[r] = 0;
-    if (active[r] && k[r] == kEmpty) {
-      res[r] = t.ctr->sentinel ? 1u : 0u;
-      done[r] = true;
-    }
-  }
-  for (;;) {
-    bool any = false;
-#pragma unroll
-    for (int r = 0; r < R; ++r) any |= !done[r];
-    if (!ballot(any)) break;
-    uint64_t v0[R], v1[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      v0[r] = v1[r] = kEmpty;
-      if (!done[r]) {
-        b[r] = probe_bucket<SCRIPTED>(t, k[r], j[r], b[r]);
-        load_pair<false>(t.slots + b[r] * (uint64_t)B + 2 * gl, v0[r], v1[r]);
-      }
-    }
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      if (!done[r]) {
-        const uint64_t eq = group_bits<B>((v0[r] == k[r]) | (v1[r] == k[r]), g0);
-        const uint64_t em = group_bits<B>((v0[r] == kEmpty) | (v1[r] == kEmpty), g0);
-        if (eq) {
-          res[r] = 1;
-          done[r] = true;
-        } else if (em) {
-          res[r] = 0;            // first non-full bucket: the key would be here
-          done[r] = true;
-        } else if (++j[r] >= nseq) {
-          uint32_t s = 0;
-          if (gl == 0) s = stash_query(t, k[r], stash_count, overflow_count) ? 1u : 0u;
-          res[r] = shfl32(s, g0);
-          done[r] = true;
-        }
-      }
-    }
-  }
-}
-
-// Grid-stride find-or-put: each wave step covers G*R keys; group g handles
-// keys base + r*G + g (consecutive groups read consecutive keys).
-template <int B, int R, bool SCRIPTED, bool COHERENT>
-__global__ __launch_bounds__(kBlock) void bucketed_fop_kernel(DevTable t, const uint64_t* __restrict__ keys,
-                                                               uint64_t n, uint8_t* __restrict__ out) {
-  using Geo = BucketGeo<B>;
-  constexpr uint64_t PER = (uint64_t)Geo::G * R;
-  const int lane = lane_id();
-  const int gl = lane & (Geo::L - 1);
-  const int grp = lane / Geo::L;
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
-  unsigned long long nnew = 0;
-  for (uint64_t base = wave * PER; base < n; base += nwaves * PER) {
-    uint64_t k[R];
-    bool act[R];
-    uint32_t res[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint64_t i = base + (uint64_t)r * Geo::G + grp;
-      act[r] = i < n;
-      k[r] = act[r] ? keys[i] : 0;
-    }
-    bucket_find_or_put<B, R, SCRIPTED, COHERENT>(t, k, act, res);
-    if (gl == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (act[r]) {
-          if (out) out[base + (uint64_t)r * Geo::G + grp] = (uint8_t)res[r];
-          nnew += (res[r] == 1);
-        }
-      }
-    }
-  }
-  wave_count(t.ctr->size, nnew, (uint32_t)wave);
-}
-
-template <int B, int R, bool SCRIPTED>
-__global__ __launch_bounds__(kBlock) void bucketed_query_kernel(DevTable t, const uint64_t* __restrict__ keys,
-                                                                 uint64_t n, uint8_t* __restrict__ out) {
-  using Geo = BucketGeo<B>;
-  constexpr uint64_t PER = (uint64_t)Geo::G * R;
-  const int lane = lane_id();
-  const int gl = lane & (Geo::L - 1);
-  const int grp = lane / Geo::L;
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
-  const uint32_t sc = t.ctr->stash_count;
-  const uint32_t oc = t.ctr->overflow_count;
-  for (uint64_t base = wave * PER; base < n; base += nwaves * PER) {
-    uint64_t k[R];
-    bool act[R];
-    uint32_t res[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint64_t i = base + (uint64_t)r * Geo::G + grp;
-      act[r] = i < n;
-      k[r] = act[r] ? keys[i] : 0;
-    }
-    bucket_query<B, R, SCRIPTED>(t, k, act, sc, oc, res);
-    if (gl == 0) {
-#pragma unroll
-      for (int r = 0; r < R; ++r)
-        if (act[r]) out[base + (uint64_t)r * Geo::G + grp] = (uint8_t)res[r];
-    }
-  }
-}
 
 // ---- host launchers --------------------------------------------------------
 

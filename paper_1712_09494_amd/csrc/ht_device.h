@@ -12,6 +12,10 @@ namespace ht {
 // word instead of a slot.
 constexpr uint64_t kEmpty = ~0ull;
 
+// Table kinds (same values as HT_BUCKETED / HT_CUCKOO of the C ABI).
+constexpr uint32_t HT_KIND_BUCKETED = 1;
+constexpr uint32_t HT_KIND_CUCKOO = 2;
+
 constexpr int kWave = 64;
 constexpr int kBlock = 256;          // 4 waves per workgroup
 constexpr int kSpread = 16;          // hot counters are spread over 16 lines

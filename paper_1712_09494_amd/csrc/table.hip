@@ -32,6 +32,24 @@ hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                          hipStream_t);
+struct MultiSpec {
+  DevTable t;
+  const uint64_t* keys;
+  uint8_t* out;
+  uint64_t n;
+};
+struct MultiTable;
+struct MultiPlanDev {
+  MultiTable* tabs = nullptr;
+  uint64_t* items = nullptr;
+  unsigned int* ctl = nullptr;
+  void* base = nullptr;
+  uint32_t nitems = 0;
+  uint32_t nctl = 0;
+};
+hipError_t multi_plan_build(const std::vector<MultiSpec>&, MultiPlanDev&);
+void multi_plan_free(MultiPlanDev&);
+hipError_t multi_plan_launch(const MultiPlanDev&, uint32_t, hipStream_t);
 hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_t);
 hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
                         hipStream_t);
@@ -167,6 +185,19 @@ struct ht_table {
   // scripted hashes
   ScriptRow* script = nullptr;
   uint32_t nscript = 0;
+};
+
+struct ht_multi_plan {
+  std::vector<ht_table*> tables;
+  MultiPlanDev dev;           // the bucketed tables' persistent launch
+  struct CuckooJob {
+    ht_table* t;
+    const uint64_t* keys;
+    uint8_t* out;
+    uint64_t n;
+  };
+  std::vector<CuckooJob> cuckoo;   // run with their own phase kernels
+  uint32_t grid = 0;
 };
 
 namespace {
@@ -358,6 +389,19 @@ DevTable launch_view(const ht_table* t) {
   return d;
 }
 
+// Scratch of a Cuckoo call with n keys (per_wave left for the caller).
+CuckooScratch scratch_view(const ht_table* t, uint64_t n) {
+  CuckooScratch sc{};
+  sc.dset = t->dset;
+  sc.dset_mask = std::min<uint64_t>(pow2_at_least(std::max<uint64_t>(2 * n, 64)), t->dset_slots) - 1;
+  sc.dset_seed = t->dset_seed;
+  sc.wkey = t->wkey;
+  sc.wmeta = t->wmeta;
+  sc.wcnt = t->wcnt;
+  sc.ccnt = t->wcnt + (uint64_t)max_blocks(t) * (kBlock / kWave);
+  return sc;
+}
+
 int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
@@ -376,14 +420,7 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
   const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
   const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
   const uint64_t nwaves = blocks * 4;
-  CuckooScratch sc;
-  sc.dset = t->dset;
-  sc.dset_mask = std::min<uint64_t>(pow2_at_least(std::max<uint64_t>(2 * n, 64)), t->dset_slots) - 1;
-  sc.dset_seed = t->dset_seed;
-  sc.wkey = t->wkey;
-  sc.wmeta = t->wmeta;
-  sc.wcnt = t->wcnt;
-  sc.ccnt = t->wcnt + (uint64_t)max_blocks(t) * (kBlock / kWave);
+  CuckooScratch sc = scratch_view(t, n);
   sc.per_wave = (n + nwaves - 1) / nwaves;
   {
     KernelTimer kt("cuckoo_probe", s);
@@ -543,15 +580,90 @@ int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_out_fou
   return do_query(t, d_keys, n, d_out_found, s);
 }
 
-int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint64_t* n,
-                         uint8_t* const* d_out_is_new, uint32_t ntables, hipStream_t s) {
-  if (ntables == 0) return HT_OK;
-  if (!t || !d_keys || !n || !d_out_is_new) return fail(HT_EINVAL, "NULL argument array");
+int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, const uint64_t* n,
+                         uint8_t* const* d_out_is_new, uint32_t ntables, ht_multi_plan** out) {
+  if (!out) return fail(HT_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (ntables && (!t || !d_keys || !n || !d_out_is_new)) return fail(HT_EINVAL, "NULL argument array");
+  if (ntables > (1u << 23)) return fail(HT_EINVAL, "too many tables in one plan");
+  std::vector<MultiSpec> specs;
+  std::vector<ht_multi_plan::CuckooJob> cuckoo;
+  std::vector<ht_table*> seen;
   for (uint32_t i = 0; i < ntables; ++i) {
-    int rc = ht_find_or_put(t[i], d_keys[i], n[i], d_out_is_new[i], s);
+    int rc = check_table(t[i]);
+    if (rc) return rc;
+    if (std::find(seen.begin(), seen.end(), t[i]) != seen.end())
+      return fail(HT_EINVAL, "a table appears twice in one multi-table call");
+    seen.push_back(t[i]);
+    if (n[i] && !d_keys[i]) return fail(HT_EINVAL, "keys is NULL");
+    if (n[i] >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
+    if (is_scripted(t[i])) return fail(HT_EINVAL, "scripted-hash tables are not supported by the multi-table call");
+    if (t[i]->cfg.kind == HT_CUCKOO) {
+      rc = reserve_scratch(t[i], n[i]);     // so that launches allocate nothing
+      if (rc) return rc;
+      if (n[i]) cuckoo.push_back({t[i], d_keys[i], d_out_is_new[i], n[i]});
+      continue;
+    }
+    MultiSpec sp{};
+    sp.t = launch_view(t[i]);
+    sp.keys = d_keys[i];
+    sp.out = d_out_is_new[i];
+    sp.n = n[i];
+    specs.push_back(sp);
+  }
+  ht_multi_plan* p = new ht_multi_plan();
+  p->tables = seen;
+  p->cuckoo = cuckoo;
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  p->grid = device_cus(dev) * 8;
+  hipError_t e = multi_plan_build(specs, p->dev);
+  if (e != hipSuccess) {
+    multi_plan_free(p->dev);
+    delete p;
+    return hip_fail(e, "multi_plan_build");
+  }
+  *out = p;
+  return HT_OK;
+}
+
+int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t s) {
+  if (!p) return fail(HT_EINVAL, "plan is NULL");
+  {
+    KernelTimer kt("multi_fill", s);
+    HT_HIP(multi_plan_launch(p->dev, p->grid, s));
+  }
+  for (const auto& j : p->cuckoo) {
+    int rc = do_find_or_put(j.t, j.keys, j.n, j.out, s);
     if (rc) return rc;
   }
   return HT_OK;
+}
+
+int ht_multi_plan_status(ht_multi_plan* p, hipStream_t s) {
+  if (!p) return fail(HT_EINVAL, "plan is NULL");
+  HT_HIP(hipStreamSynchronize(s));
+  return HT_OK;
+}
+
+int ht_multi_plan_destroy(ht_multi_plan* p) {
+  if (!p) return fail(HT_EINVAL, "plan is NULL");
+  (void)hipDeviceSynchronize();
+  multi_plan_free(p->dev);
+  delete p;
+  return HT_OK;
+}
+
+int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint64_t* n,
+                         uint8_t* const* d_out_is_new, uint32_t ntables, hipStream_t s) {
+  if (ntables == 0) return HT_OK;
+  ht_multi_plan* p = nullptr;
+  int rc = ht_multi_plan_create(t, d_keys, n, d_out_is_new, ntables, &p);
+  if (rc) return rc;
+  rc = ht_multi_plan_launch(p, s);
+  if (!rc) rc = ht_multi_plan_status(p, s);
+  ht_multi_plan_destroy(p);
+  return rc;
 }
 
 int ht_sync_status(ht_table* t, hipStream_t s) {

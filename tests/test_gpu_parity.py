@@ -241,20 +241,3 @@ def test_flags_optional_and_clear():
         assert t.size() == 0 and not run_query(t, keys).any()
         assert run_fop(t, keys).all()
         t.close()
-
-
-def test_multi_equals_single():
-    rng = np.random.default_rng(5)
-    tables, keys, expect = [], [], []
-    for i in range(12):
-        design = ["bkt16", "bkt8", "cuckoo", "bkt32"][i % 4]
-        n = int(rng.integers(1, 50000))
-        k = inputs.key_of_index(rng.integers(0, n, size=n), seed=i)
-        tables.append(make(design, int(n / 0.6) + 16))
-        keys.append(k)
-        expect.append(first_occurrence_flags(k))
-    outs = b.find_or_put_multi(tables, [dev(k) for k in keys])
-    for i, t in enumerate(tables):
-        check_flags_r2(keys[i], host(outs[i]), expect[i], f"multi table {i}")
-        check_dump_r3(dump_u64(t), np.unique(keys[i]), t.size(), f"multi table {i}")
-        t.close()

@@ -241,6 +241,76 @@ const char* ht_strerror(int code);
  * argument check), "" if none. */
 const char* ht_last_error(void);
 
+/* ---- serving: a request loop over resident tables ----------------------- */
+
+enum {
+  HT_OP_FIND_OR_PUT = 1,
+  HT_OP_QUERY = 2
+};
+
+/* One request of a served trace.  Keys and flags are HOST buffers that must
+ * be pinned (hipHostMalloc, or torch's pin_memory); the engine copies keys
+ * in and flags out on its own streams.  arrival_s is the release time in
+ * seconds after ht_server_run starts; the engine fills admit_s, done_s
+ * (completion seen by the host, same clock), slot and group. */
+typedef struct {
+  uint32_t op;              /* HT_OP_FIND_OR_PUT or HT_OP_QUERY */
+  uint32_t table;           /* index into the server's tables */
+  const uint64_t* h_keys;
+  uint64_t n;
+  uint8_t* h_out;           /* n flags: as ht_find_or_put / ht_query */
+  double arrival_s;
+  double admit_s;
+  double done_s;
+  uint32_t slot;
+  uint32_t group;
+} ht_request;
+
+typedef struct {
+  uint32_t slots;           /* launch groups in flight at once (streams), 1..16; 0 = 16 */
+  uint32_t merge;           /* requests of distinct tables per launch group; 0 = 16 */
+  uint64_t staging_bytes;   /* device staging budget for admission (9 bytes per key,
+                               256-byte pieces); 0 = min(free device memory / 4, 4 GiB) */
+  uint32_t sequential;      /* 1 = baseline: one request at a time, waiting for each */
+  uint32_t reserved;
+  uint64_t group_keys;      /* a group stops taking requests at this many keys
+                               (its first request is always taken); 0 = 2^19 */
+} ht_server_config;
+
+typedef struct {
+  double wall_s;            /* run start to the last completion */
+  uint64_t keys;            /* keys in the trace */
+  uint64_t peak_staging;    /* largest staging in use at once, bytes */
+  uint64_t staging_bytes;   /* the budget */
+  uint32_t groups;          /* launch groups issued */
+  uint32_t merged_launches; /* many-table launches among them */
+  uint32_t max_inflight_groups;
+  uint32_t throttled;       /* admissions deferred for lack of staging */
+} ht_server_stats;
+
+typedef struct ht_server ht_server;
+
+void ht_server_config_default(ht_server_config* cfg);
+
+/* Serve `ntables` resident tables (the tables stay owned by the caller and
+ * must outlive the server).  Allocates the staging budget, stream slots and
+ * their events.  HT_EINVAL for scripted-hash tables or bad configs. */
+int ht_server_create(ht_table* const* tables, uint32_t ntables, const ht_server_config* cfg,
+                     ht_server** out);
+
+/* Replay `nreq` requests: each is released at its arrival time, admitted in
+ * arrival order per table (FIFO) when its table is idle, a stream slot is
+ * free and its staging fits, merged with admissible requests of other
+ * tables into one launch group, and retired when the group's event
+ * completes.  Each result equals the one the request gets when its table's
+ * requests run one by one in arrival order.  Blocks until every request is
+ * done; fills the per-request times and *stats (may be NULL).  Reserves
+ * Cuckoo scratch for the largest request before starting the clock. */
+int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats* stats);
+
+/* Free the server (synchronises the device); the tables are untouched. */
+int ht_server_destroy(ht_server* s);
+
 /* ---- kernel timing (measurement aid) ------------------------------------ */
 
 /* Enable (on != 0) or disable per-kernel timing and reset the figures.  When

@@ -67,6 +67,52 @@ class HtConfig(C.Structure):
     ]
 
 
+class HtRequest(C.Structure):
+    _fields_ = [
+        ("op", C.c_uint32),
+        ("table", C.c_uint32),
+        ("h_keys", C.c_void_p),
+        ("n", C.c_uint64),
+        ("h_out", C.c_void_p),
+        ("arrival_s", C.c_double),
+        ("admit_s", C.c_double),
+        ("done_s", C.c_double),
+        ("slot", C.c_uint32),
+        ("group", C.c_uint32),
+    ]
+
+
+class HtServerConfig(C.Structure):
+    _fields_ = [
+        ("slots", C.c_uint32),
+        ("merge", C.c_uint32),
+        ("staging_bytes", C.c_uint64),
+        ("sequential", C.c_uint32),
+        ("reserved", C.c_uint32),
+        ("group_keys", C.c_uint64),
+    ]
+
+
+class HtServerStats(C.Structure):
+    _fields_ = [
+        ("wall_s", C.c_double),
+        ("keys", C.c_uint64),
+        ("peak_staging", C.c_uint64),
+        ("staging_bytes", C.c_uint64),
+        ("groups", C.c_uint32),
+        ("merged_launches", C.c_uint32),
+        ("max_inflight_groups", C.c_uint32),
+        ("throttled", C.c_uint32),
+    ]
+
+    def as_dict(self) -> dict:
+        return {f: getattr(self, f) for f, _ in self._fields_}
+
+
+HT_OP_FIND_OR_PUT = 1
+HT_OP_QUERY = 2
+
+
 class HtStats(C.Structure):
     _fields_ = [
         ("size", C.c_uint64),
@@ -116,6 +162,10 @@ _PROTOS = {
     "ht_reserve": (C.c_int, [_vp, _u64]),
     "ht_strerror": (C.c_char_p, [C.c_int]),
     "ht_last_error": (C.c_char_p, []),
+    "ht_server_config_default": (None, [C.POINTER(HtServerConfig)]),
+    "ht_server_create": (C.c_int, [C.POINTER(_vp), _u32, C.POINTER(HtServerConfig), C.POINTER(_vp)]),
+    "ht_server_run": (C.c_int, [_vp, C.POINTER(HtRequest), _u32, C.POINTER(HtServerStats)]),
+    "ht_server_destroy": (C.c_int, [_vp]),
     "ht_timing_enable": (C.c_int, [C.c_int]),
     "ht_timing_report": (C.c_int, [C.c_char_p, _u64]),
     "ht_probe_copy": (C.c_int, [_vp, _vp, _u64, _vp]),
@@ -476,6 +526,70 @@ class Table:
 
     def reserve(self, max_batch: int) -> None:
         ht_reserve(self.handle, max_batch)
+
+
+class Server:
+    """Request loop over resident tables (ht_server_*).
+
+    run(reqs) takes a list of (op, table_index, keys, arrival_s) where keys is
+    a pinned host tensor (int64/uint64; see torch's pin_memory); it returns a
+    list of pinned host uint8 flag tensors, per-request admit/done times and
+    the run statistics."""
+
+    def __init__(self, tables, slots: int = 16, merge: int = 16, staging_bytes: int = 0,
+                 sequential: bool = False, group_keys: int = 0):
+        n = len(tables)
+        self.tables = list(tables)
+        cfg = HtServerConfig()
+        load().ht_server_config_default(C.byref(cfg))
+        cfg.slots = int(slots)
+        cfg.merge = int(merge)
+        cfg.staging_bytes = int(staging_bytes)
+        cfg.sequential = 1 if sequential else 0
+        cfg.group_keys = int(group_keys)
+        th = (_vp * n)(*[t.handle for t in self.tables])
+        h = _vp()
+        _check(load().ht_server_create(th, n, C.byref(cfg), C.byref(h)), "ht_server_create")
+        self.handle = h.value
+
+    def run(self, reqs, outs=None):
+        torch = _torch()
+        n = len(reqs)
+        arr = (HtRequest * max(n, 1))()
+        keep = []
+        outs = outs or [None] * n
+        res = []
+        for i, (op, table, keys, arrival) in enumerate(reqs):
+            if keys.device.type != "cpu" or not keys.is_pinned():
+                raise ValueError("request keys must be a pinned host tensor")
+            o = outs[i]
+            if o is None:
+                o = torch.empty(keys.numel(), dtype=torch.uint8, pin_memory=True)
+            keep.append(keys)
+            res.append(o)
+            arr[i].op = HT_OP_QUERY if op == "query" else HT_OP_FIND_OR_PUT
+            arr[i].table = int(table)
+            arr[i].h_keys = keys.data_ptr() if keys.numel() else None
+            arr[i].n = keys.numel()
+            arr[i].h_out = o.data_ptr() if keys.numel() else None
+            arr[i].arrival_s = float(arrival)
+        st = HtServerStats()
+        _check(load().ht_server_run(self.handle, arr, n, C.byref(st)), "ht_server_run")
+        admit = np.array([arr[i].admit_s for i in range(n)])
+        done = np.array([arr[i].done_s for i in range(n)])
+        groups = np.array([arr[i].group for i in range(n)])
+        return res, admit, done, groups, st.as_dict()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _check(load().ht_server_destroy(self.handle), "ht_server_destroy")
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def find_or_put_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):

@@ -1,15 +1,18 @@
 // Many bucketed tables in one persistent launch.
 //
-// The find-or-put of every bucketed table is cut into work items of 4096
-// keys; resident waves take items in queue order through one atomic counter
-// and run the same wave-level bucket probe as the single-table kernel, with
-// the bucket width taken from each table at run time (one code path for
-// 8/16/32/64 slots, one key per lane group in flight, so the kernel keeps
-// the occupancy of the single-table kernels).  Items never wait on each
-// other, so the queue drains as fast as the waves work.  Tables may mix
-// bucket widths and hash counts; each uses its own storage, so the results
-// equal one find-or-put call per table.  The launch allocates nothing and
-// uses no memset, so it can be captured in a HIP graph.
+// The find-or-put of every bucketed table is cut into work items of equal
+// size (a power of two between 256 and 4096 keys, chosen so that a launch has
+// about as many items as the device has wave slots); wave w takes items w,
+// w + W, w + 2W, ... of the queue.  The items are equal, so this static
+// split balances, and it needs no shared queue counter (a counter popped by
+// every wave of a large grid serialises on one address).  Each wave runs the
+// same wave-level bucket probe as the single-table kernel, with the bucket
+// width taken from each table at run time (one code path for 8/16/32/64
+// slots, one key per lane group in flight, so the kernel keeps the
+// occupancy of the single-table kernels).  Tables may mix bucket widths and
+// hash counts; each uses its own storage, so the results equal one
+// find-or-put call per table.  The launch allocates nothing and uses no
+// memset, so it can be captured in a HIP graph.
 //
 // Cuckoo tables of a many-table call run their four phase kernels per table
 // after this kernel, in the same stream order (see the host runtime): their
@@ -18,6 +21,7 @@
 #include <vector>
 
 #include "bucketed_dev.h"
+#include "multi.h"
 
 namespace ht {
 
@@ -37,21 +41,11 @@ __host__ __device__ inline uint64_t make_item(uint32_t table, uint64_t region) {
   return ((uint64_t)table << 40) | region;
 }
 
-// ctl[0]: queue head
-__global__ void multi_reset_kernel(unsigned int* ctl, uint32_t nwords) {
-  for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) ctl[i] = 0u;
-}
-
 __global__ __launch_bounds__(kBlock) void multi_fill_kernel(const MultiTable* __restrict__ tabs,
-                                                            const uint64_t* __restrict__ items, uint32_t nitems,
-                                                            unsigned int* ctl) {
-  const int lane = lane_id();
+                                                            const uint64_t* __restrict__ items, uint32_t nitems) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  for (;;) {
-    unsigned int idx = 0;
-    if (lane == 0) idx = add_agent(&ctl[0], 1u);
-    idx = __builtin_amdgcn_readfirstlane(idx);
-    if (idx >= nitems) break;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t idx = wave; idx < nitems; idx += nwaves) {
     // uniform across the wave: keep the item (and so the table descriptor's
     // address) in scalar registers
     const uint64_t raw = items[idx];
@@ -65,14 +59,20 @@ __global__ __launch_bounds__(kBlock) void multi_fill_kernel(const MultiTable* __
   }
 }
 
-// ---- host side ------------------------------------------------------------
+// Item size for a launch of `total` keys on a device with `max_waves` wave
+// slots: a power of two in [256, 4096] giving about max_waves items.
+uint64_t multi_chunk(uint64_t total, uint64_t max_waves) {
+  uint64_t c = 256;
+  while (c < 4096 && c * max_waves < total) c <<= 1;
+  return c;
+}
 
-struct MultiSpec {
-  DevTable t;
-  const uint64_t* keys;
-  uint8_t* out;
-  uint64_t n;
-};
+uint32_t multi_grid(uint64_t nitems, uint32_t max_blocks) {
+  const uint64_t blocks = (nitems + (kBlock / kWave) - 1) / (kBlock / kWave);
+  return (uint32_t)(blocks < max_blocks ? (blocks ? blocks : 1) : max_blocks);
+}
+
+// ---- host side ------------------------------------------------------------
 
 struct MultiPlanDev {
   MultiTable* tabs = nullptr;
@@ -81,14 +81,18 @@ struct MultiPlanDev {
   void* base = nullptr;
   uint32_t nitems = 0;
   uint32_t nctl = 0;
+  uint32_t grid = 0;
 };
 
 // Build descriptors and the item queue on the host and copy them to one
 // device allocation (synchronous).  Returns hipSuccess or the HIP error.
-hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, MultiPlanDev& plan) {
+hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, uint32_t max_blocks, MultiPlanDev& plan) {
   const uint32_t nt = (uint32_t)specs.size();
   std::vector<MultiTable> tabs(nt);
   std::vector<uint64_t> items;
+  uint64_t total = 0;
+  for (const auto& sp : specs) total += sp.n;
+  const uint64_t chunk = multi_chunk(total, (uint64_t)max_blocks * (kBlock / kWave));
   for (uint32_t i = 0; i < nt; ++i) {
     const MultiSpec& sp = specs[i];
     MultiTable& m = tabs[i];
@@ -97,12 +101,13 @@ hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, MultiPlanDev& p
     m.keys = sp.keys;
     m.out = sp.out;
     m.n = sp.n;
-    m.chunk = 4096;
+    m.chunk = chunk;
     m.nregions = sp.n ? (uint32_t)((sp.n + m.chunk - 1) / m.chunk) : 0;
     for (uint64_t r = 0; r < m.nregions; ++r) items.push_back(make_item(i, r));
   }
   plan.nitems = (uint32_t)items.size();
-  plan.nctl = 2;
+  plan.grid = multi_grid(plan.nitems, max_blocks);
+  plan.nctl = 0;
   const size_t b_tabs = (sizeof(MultiTable) * nt + 255) / 256 * 256;
   const size_t b_items = (items.size() * 8 + 255) / 256 * 256;
   const size_t b_ctl = 256;
@@ -123,13 +128,71 @@ void multi_plan_free(MultiPlanDev& plan) {
   plan = MultiPlanDev{};
 }
 
-hipError_t multi_plan_launch(const MultiPlanDev& plan, uint32_t grid, hipStream_t s) {
+hipError_t multi_plan_launch(const MultiPlanDev& plan, hipStream_t s) {
   if (plan.nitems == 0) return hipSuccess;
-  hipLaunchKernelGGL(multi_reset_kernel, dim3(1), dim3(kBlock), 0, s, plan.ctl, plan.nctl);
-  hipError_t e = hipGetLastError();
+  hipLaunchKernelGGL(multi_fill_kernel, dim3(plan.grid), dim3(kBlock), 0, s, plan.tabs, plan.items, plan.nitems);
+  return hipGetLastError();
+}
+
+// ---- per-launch descriptors (serving loop) -----------------------------------
+// A launch whose table set changes every time: descriptors and items are
+// written into pinned host buffers owned by one stream slot and copied to
+// that slot's device buffers on the launch stream, so nothing is allocated
+// per launch.  The caller reuses a slot only after its previous launch has
+// completed.
+
+hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items) {
+  d.cap_tabs = cap_tabs;
+  d.cap_items = cap_items;
+  const size_t b_tabs = (sizeof(MultiTable) * cap_tabs + 255) / 256 * 256;
+  const size_t b_items = ((size_t)cap_items * 8 + 255) / 256 * 256;
+  hipError_t e = hipMalloc(&d.d_base, b_tabs + b_items + 256);
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(multi_fill_kernel, dim3(grid), dim3(kBlock), 0, s, plan.tabs, plan.items, plan.nitems,
-                     plan.ctl);
+  e = hipHostMalloc(&d.h_base, b_tabs + b_items, hipHostMallocDefault);
+  if (e != hipSuccess) return e;
+  char* c = static_cast<char*>(d.d_base);
+  d.d_tabs = reinterpret_cast<MultiTable*>(c);
+  d.d_items = reinterpret_cast<uint64_t*>(c + b_tabs);
+  d.d_ctl = reinterpret_cast<unsigned int*>(c + b_tabs + b_items);
+  char* h = static_cast<char*>(d.h_base);
+  d.h_tabs = reinterpret_cast<MultiTable*>(h);
+  d.h_items = reinterpret_cast<uint64_t*>(h + b_tabs);
+  return hipSuccess;
+}
+
+void multi_dyn_free(MultiDyn& d) {
+  if (d.d_base) (void)hipFree(d.d_base);
+  if (d.h_base) (void)hipHostFree(d.h_base);
+  d = MultiDyn{};
+}
+
+// Number of work items a table of n keys needs.
+uint64_t multi_items_for(uint64_t n) { return (n + 255) / 256; }
+
+hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, uint32_t max_blocks, hipStream_t s) {
+  if (nt > d.cap_tabs) return hipErrorInvalidValue;
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < nt; ++i) total += specs[i].n;
+  const uint64_t chunk = multi_chunk(total, (uint64_t)max_blocks * (kBlock / kWave));
+  uint32_t nitems = 0;
+  for (uint32_t i = 0; i < nt; ++i) {
+    MultiTable& m = d.h_tabs[i];
+    std::memset(&m, 0, sizeof(m));
+    m.t = specs[i].t;
+    m.keys = specs[i].keys;
+    m.out = specs[i].out;
+    m.n = specs[i].n;
+    m.chunk = chunk;
+    m.nregions = (uint32_t)((specs[i].n + chunk - 1) / chunk);
+    if (nitems + m.nregions > d.cap_items) return hipErrorInvalidValue;
+    for (uint64_t r = 0; r < m.nregions; ++r) d.h_items[nitems++] = make_item(i, r);
+  }
+  if (nitems == 0) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(d.d_tabs, d.h_tabs, sizeof(MultiTable) * nt, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) e = hipMemcpyAsync(d.d_items, d.h_items, (size_t)nitems * 8, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(multi_fill_kernel, dim3(multi_grid(nitems, max_blocks)), dim3(kBlock), 0, s, d.d_tabs,
+                     d.d_items, nitems);
   return hipGetLastError();
 }
 

@@ -9,8 +9,8 @@
 #include <string>
 #include <vector>
 
-#include "ht_device.h"
-#include "../../include/ht.h"
+#include "multi.h"
+#include "runtime.h"
 
 namespace ht {
 // kernels (bucketed.hip, cuckoo.hip, util.hip, multi.hip)
@@ -32,13 +32,6 @@ hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                          hipStream_t);
-struct MultiSpec {
-  DevTable t;
-  const uint64_t* keys;
-  uint8_t* out;
-  uint64_t n;
-};
-struct MultiTable;
 struct MultiPlanDev {
   MultiTable* tabs = nullptr;
   uint64_t* items = nullptr;
@@ -46,10 +39,11 @@ struct MultiPlanDev {
   void* base = nullptr;
   uint32_t nitems = 0;
   uint32_t nctl = 0;
+  uint32_t grid = 0;
 };
-hipError_t multi_plan_build(const std::vector<MultiSpec>&, MultiPlanDev&);
+hipError_t multi_plan_build(const std::vector<MultiSpec>&, uint32_t, MultiPlanDev&);
 void multi_plan_free(MultiPlanDev&);
-hipError_t multi_plan_launch(const MultiPlanDev&, uint32_t, hipStream_t);
+hipError_t multi_plan_launch(const MultiPlanDev&, hipStream_t);
 hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_t);
 hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
                         hipStream_t);
@@ -57,8 +51,9 @@ hipError_t probe_cas(uint64_t*, uint64_t, uint64_t, uint64_t, uint32_t, hipStrea
 }  // namespace ht
 
 using namespace ht;
+using namespace ht_rt;
 
-namespace {
+namespace ht_rt {
 
 thread_local std::string g_err;
 
@@ -77,14 +72,6 @@ int hip_fail(hipError_t e, const char* what) {
     hipError_t e_ = (call);                            \
     if (e_ != hipSuccess) return hip_fail(e_, #call);  \
   } while (0)
-
-struct SplitMix {
-  uint64_t s;
-  uint64_t next() {
-    s += 0x9e3779b97f4a7c15ull;
-    return mix64(s);
-  }
-};
 
 // Compute units of the current device (cached per device id).
 uint32_t device_cus(int dev) {
@@ -162,30 +149,8 @@ void resolve_timings() {
   g_pending.clear();
 }
 
-}  // namespace
+}  // namespace ht_rt
 
-struct ht_table {
-  ht_config cfg;             // effective configuration (defaults filled in)
-  ht_config user_cfg;        // as passed to ht_create
-  int device = 0;
-  uint32_t cus = 256;
-  uint64_t nslots = 0;       // total slot words
-  DevTable dev{};
-  SplitMix rng{0};
-  void* storage = nullptr;   // slots | stash | overflow | counters | misc
-  unsigned long long* misc = nullptr;
-  // cuckoo scratch
-  uint64_t scratch_n = 0;
-  uint64_t dset_slots = 0;
-  uint64_t dset_seed = 0;
-  uint64_t* dset = nullptr;
-  uint64_t* wkey = nullptr;
-  uint64_t* wmeta = nullptr;
-  uint32_t* wcnt = nullptr;
-  // scripted hashes
-  ScriptRow* script = nullptr;
-  uint32_t nscript = 0;
-};
 
 struct ht_multi_plan {
   std::vector<ht_table*> tables;
@@ -200,7 +165,7 @@ struct ht_multi_plan {
   uint32_t grid = 0;
 };
 
-namespace {
+namespace ht_rt {
 
 uint32_t max_blocks(const ht_table* t) { return t->cus * 8; }
 
@@ -487,7 +452,7 @@ int dump_members(ht_table* t, uint64_t** d_buf, uint64_t* count, hipStream_t s) 
   return HT_OK;
 }
 
-}  // namespace
+}  // namespace ht_rt
 
 // ============================================================================
 // C ABI
@@ -617,7 +582,7 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
   int dev = 0;
   (void)hipGetDevice(&dev);
   p->grid = device_cus(dev) * 8;
-  hipError_t e = multi_plan_build(specs, p->dev);
+  hipError_t e = multi_plan_build(specs, p->grid, p->dev);
   if (e != hipSuccess) {
     multi_plan_free(p->dev);
     delete p;
@@ -631,7 +596,7 @@ int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t s) {
   if (!p) return fail(HT_EINVAL, "plan is NULL");
   {
     KernelTimer kt("multi_fill", s);
-    HT_HIP(multi_plan_launch(p->dev, p->grid, s));
+    HT_HIP(multi_plan_launch(p->dev, s));
   }
   for (const auto& j : p->cuckoo) {
     int rc = do_find_or_put(j.t, j.keys, j.n, j.out, s);

@@ -336,3 +336,63 @@ class BfsModel:
         m = np.stack(cols, axis=1)
         v = np.stack(valid, axis=1)
         return m[v]
+
+
+# --------------------------------------------------------------------------
+# served request traces
+# --------------------------------------------------------------------------
+
+def successor_stream(model: "BfsModel", min_keys: int, start_states=(0,)) -> np.ndarray:
+    """Successor batches expanded level by level from `start_states` without
+    removing duplicates (a state reached along several paths appears several
+    times), concatenated until at least `min_keys` keys are produced."""
+    out, total = [], 0
+    for s0 in start_states:
+        frontier = np.array([s0], dtype=np.uint64)
+        while total < min_keys and frontier.size:
+            batch = model.successors(frontier)
+            out.append(batch)
+            total += batch.size
+            frontier = batch[: max(1, min_keys - total)]
+        if total >= min_keys:
+            break
+    return np.concatenate(out) if out else np.zeros(0, dtype=np.uint64)
+
+
+def served_trace(nreq: int, ntables: int, log_min: float = 8, log_max: float = 20, rate: float = 0.0,
+                 seed: int = SEED_BASE + 5, bfs_frac: float = 0.7, query_frac: float = 0.5,
+                 stream: np.ndarray | None = None):
+    """Requests for a served run: list of (op, table, keys, arrival_s).
+
+    Sizes floor(2^U), U uniform in [log_min, log_max]; op is "query" with
+    probability query_frac, else "fop"; table uniform; keys: the first
+    round(bfs_frac * n) from the table's cursor into a shared successor
+    stream (find-or-puts advance the cursor, queries read ahead of it without
+    advancing), the rest fresh random keys.  Arrivals are a Poisson process
+    of `rate` requests per second (all at 0 when rate is 0).
+    """
+    r = SplitMix64(seed)
+    u01 = lambda: (r.next() >> 11) * (1.0 / (1 << 53))
+    if stream is None:
+        stream = successor_stream(BfsModel(1), 1 << 22, start_states=(0, 0x123456789ABCDEF))
+    ns = max(1, stream.size)
+    cursor = [(t * 1000003) % ns for t in range(ntables)]
+    fresh = 0
+    t_arr = 0.0
+    reqs = []
+    for i in range(nreq):
+        n = int(2.0 ** (log_min + (log_max - log_min) * u01()))
+        op = "query" if u01() < query_frac else "fop"
+        t = int(u01() * ntables) % ntables
+        nb = int(round(bfs_frac * n))
+        idx = (cursor[t] + np.arange(nb, dtype=np.int64)) % ns
+        bfs = stream[idx]
+        if op == "fop":
+            cursor[t] = (cursor[t] + nb) % ns
+        rnd = uniform_keys(n - nb, seed ^ 0x5EED, start=fresh)
+        fresh += n - nb
+        keys = np.concatenate([bfs, rnd])
+        if rate > 0:
+            t_arr += -np.log(max(u01(), 1e-300)) / rate
+        reqs.append((op, t, keys, t_arr))
+    return reqs

@@ -1,0 +1,118 @@
+"""GPU: the served request loop (continuous batching over resident tables).
+
+Each result equals the one the request gets when its table's requests run
+one by one in arrival order (per-table FIFO), and equals the oracle's."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from paper_1712_09494_amd import binding as b  # noqa: E402
+from paper_1712_09494_amd import inputs  # noqa: E402
+from parity import check_flags_r2, check_query_r1  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+SPECS = [("bucketed", dict(bucket_slots=8)), ("bucketed", dict(bucket_slots=16)), ("cuckoo", dict())]
+
+
+def make_tables(ntables, cap):
+    return [b.Table(SPECS[i % len(SPECS)][0], capacity=cap, **SPECS[i % len(SPECS)][1]) for i in range(ntables)]
+
+
+def pinned(a):
+    t = torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).pin_memory()
+    assert t.is_pinned()
+    return t
+
+
+def alone(reqs, ntables, cap):
+    """Each table's requests one by one, in arrival order, with plain calls."""
+    tables = make_tables(ntables, cap)
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i][3])
+    res = [None] * len(reqs)
+    for i in order:
+        op, t, keys, _ = reqs[i]
+        if keys.size == 0:
+            res[i] = np.zeros(0, np.uint8)
+            continue
+        k = torch.from_numpy(keys.view(np.int64)).cuda()
+        out = tables[t].query(k) if op == "query" else tables[t].find_or_put(k)
+        res[i] = out.cpu().numpy()
+    dumps = [np.sort(b.u64(t.dump())) for t in tables]
+    for t in tables:
+        t.close()
+    return res, dumps
+
+
+def oracle_run(reqs, ntables):
+    os_ = [Oracle() for _ in range(ntables)]
+    order = sorted(range(len(reqs)), key=lambda i: reqs[i][3])
+    res = [None] * len(reqs)
+    for i in order:
+        op, t, keys, _ = reqs[i]
+        res[i] = os_[t].query(keys) if op == "query" else os_[t].find_or_put(keys)
+    return res, os_
+
+
+def compare(reqs, got, ref, what):
+    for i, (op, t, keys, _) in enumerate(reqs):
+        g = got[i]
+        if op == "query":
+            check_query_r1(g, ref[i], f"{what} req {i}")
+        else:
+            check_flags_r2(keys, g, ref[i], f"{what} req {i}")
+
+
+@pytest.mark.parametrize("cfg", [dict(slots=4, merge=8), dict(slots=2, merge=1), dict(sequential=True),
+                                 dict(slots=8, merge=16)])
+@pytest.mark.parametrize("rate", [0.0, 20000.0])
+def test_served_equals_alone_and_oracle(cfg, rate):
+    ntables, cap = 7, 1 << 16
+    reqs = inputs.served_trace(240, ntables, log_min=4, log_max=13, rate=rate, seed=11)
+    tables = make_tables(ntables, cap)
+    srv = b.Server(tables, **cfg)
+    outs, admit, done, groups, st = srv.run([(op, t, pinned(k), a) for op, t, k, a in reqs])
+    got = [o.numpy() for o in outs]
+    assert (done >= admit).all() and (admit >= np.array([r[3] for r in reqs]) - 1e-9).all()
+    ref, dumps = alone(reqs, ntables, cap)
+    compare(reqs, got, ref, f"served vs alone {cfg}")
+    ora, os_ = oracle_run(reqs, ntables)
+    compare(reqs, got, ora, f"served vs oracle {cfg}")
+    for t in range(ntables):
+        d = np.sort(b.u64(tables[t].dump()))
+        assert np.array_equal(d, dumps[t]) and np.array_equal(d, os_[t].dump())
+    if not cfg.get("sequential") and cfg.get("merge", 16) > 1 and rate == 0.0:
+        assert st["merged_launches"] > 0
+    srv.close()
+    for t in tables:
+        t.close()
+
+
+def test_served_admission_throttles_without_changing_results():
+    ntables, cap = 5, 1 << 15
+    reqs = inputs.served_trace(120, ntables, log_min=8, log_max=12, seed=12)
+    biggest = max(k.size for _, _, k, _ in reqs)
+    budget = 2 * (((biggest * 8 + 255) // 256) * 256 + ((biggest + 255) // 256) * 256)
+    tables = make_tables(ntables, cap)
+    srv = b.Server(tables, slots=4, merge=8, staging_bytes=budget)
+    outs, admit, done, groups, st = srv.run([(op, t, pinned(k), a) for op, t, k, a in reqs])
+    assert st["throttled"] > 0 and st["peak_staging"] <= budget
+    ora, _ = oracle_run(reqs, ntables)
+    compare(reqs, [o.numpy() for o in outs], ora, "throttled")
+    srv.close()
+    for t in tables:
+        t.close()
+
+
+def test_served_rejects_bad_requests():
+    t = b.Table("bucketed", capacity=1024)
+    srv = b.Server([t])
+    k = pinned(inputs.uniform_keys(10, seed=1))
+    with pytest.raises(b.HtError):
+        srv.run([("fop", 3, k, 0.0)])                  # no such table
+    with pytest.raises(ValueError):
+        srv.run([("fop", 0, torch.zeros(4, dtype=torch.int64), 0.0)])   # not pinned
+    srv.close()
+    t.close()

@@ -106,3 +106,17 @@ def test_bfs_model_shape():
     assert len(m.syncs) == 4
     for (p, q, pe, qe) in m.syncs:
         assert p != q
+
+
+def test_served_trace_shape():
+    reqs = inputs.served_trace(200, 9, log_min=4, log_max=10, rate=1000.0, seed=3)
+    assert len(reqs) == 200
+    arr = [a for _, _, _, a in reqs]
+    assert arr == sorted(arr) and arr[0] > 0
+    for op, t, k, a in reqs:
+        assert op in ("fop", "query") and 0 <= t < 9
+        assert 16 <= k.size < 1024 and k.dtype == np.uint64
+    again = inputs.served_trace(200, 9, log_min=4, log_max=10, rate=1000.0, seed=3)
+    assert all(np.array_equal(x[2], y[2]) and x[:2] == y[:2] for x, y in zip(reqs, again))
+    ops = [op for op, *_ in reqs]
+    assert 60 < ops.count("query") < 140

@@ -55,6 +55,9 @@ def parse():
     ap.add_argument("--served-only", action="store_true",
                     help="only run the served request-loop measurement")
     ap.add_argument("--served-requests", type=int, default=1024)
+    ap.add_argument("--no-bfs", action="store_true")
+    ap.add_argument("--bfs-only", action="store_true",
+                    help="only run the BFS-key (state-space exploration) measurement")
     ap.add_argument("--batched-only", action="store_true",
                     help="only run the many-table (batched) measurement")
     ap.add_argument("--probes", action="store_true",
@@ -80,6 +83,9 @@ def main():
     stream = torch.cuda.current_stream()
     if args.probes:
         print(json.dumps({"probes": run_probes(b, torch, dev, stream)}), flush=True)
+        return
+    if args.bfs_only:
+        print(json.dumps({"bfs": run_bfs(b, inputs, torch)}), flush=True)
         return
     if args.served_only:
         print(json.dumps({"served": run_served(b, inputs, torch, dev, args.served_requests)}), flush=True)
@@ -188,6 +194,10 @@ def main():
     if not args.no_batched:
         batched = run_batched(b, inputs, torch, dev, stream)
 
+    bfs = None
+    if not args.no_bfs:
+        bfs = run_bfs(b, inputs, torch)
+
     served = None
     if not args.no_served:
         served = run_served(b, inputs, torch, dev, args.served_requests)
@@ -222,6 +232,7 @@ def main():
         "sweep": sweep,
         "batched": batched,
         "served": served,
+        "bfs": bfs,
     }
     for t in tables.values():
         t.close()
@@ -496,6 +507,30 @@ def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
         plan.close()
         for t in tables:
             t.close()
+    return res
+
+
+def run_bfs(b, inputs, torch, levels=7, lf=0.7):
+    """BFS-key workload: breadth-first exploration of the synthetic 16-process
+    model (seed 1) on the GPU, each level's successor batch (duplicates
+    included) one find-or-put into a table sized for the final state count at
+    load factor 0.7.  Successor generation and frontier selection are outside
+    the timed find-or-put calls."""
+    final_states = 121210369          # states reached after level 6 (seed 1)
+    res = {"levels": levels, "load_factor": lf, "designs": {}}
+    for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+        with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=3, **kw) as t:
+            r = t.bfs_explore(inputs.BfsModel(1), levels)
+            keys = sum(r["batch_sizes"])
+            ms = sum(r["fop_ms"])
+            res["designs"][kind] = {
+                "batch_sizes": r["batch_sizes"], "new_counts": r["new_counts"],
+                "states": 1 + sum(r["new_counts"]),
+                "fop_ms": [round(x, 3) for x in r["fop_ms"]],
+                "fop_mops_per_level": [round(n / max(x, 1e-9) / 1e3, 1) for n, x in zip(r["batch_sizes"], r["fop_ms"])],
+                "fop_mops": round(keys / ms / 1e3, 1),
+                "occurrences_per_state": round(keys / max(1, sum(r["new_counts"])), 2)}
+        log(f"[bench] bfs {kind}: {res['designs'][kind]['fop_mops']} Mops/s, states {res['designs'][kind]['states']}")
     return res
 
 

@@ -241,6 +241,33 @@ const char* ht_strerror(int code);
  * argument check), "" if none. */
 const char* ht_last_error(void);
 
+/* ---- breadth-first exploration with a table as the visited set ---------- */
+
+/* A synthetic concurrent model: 16 processes with 16 local states each, the
+ * state vector packed 4 bits per process (process p in bits 4p..4p+3).
+ * local_target[p][s][0 .. local_count[p][s]-1] are the local transitions of
+ * process p in local state s (count <= 4); synchronising action a moves
+ * processes sync_p[a] and sync_q[a] together, along their edges
+ * sync_p_edge[a][s] / sync_q_edge[a][s] (-1: no edge from s). */
+typedef struct {
+  uint8_t local_count[16][16];
+  uint8_t local_target[16][16][4];
+  uint8_t sync_p[4], sync_q[4];
+  int8_t sync_p_edge[4][16], sync_q_edge[4][16];
+} ht_bfs_model;
+
+/* Breadth-first exploration from `initial` for up to `levels` levels with
+ * table `t` as the visited set (GPUexplore's use of the table, Sec. 3.2):
+ * the initial state is find-or-put first; at each level the successors of
+ * the frontier are generated on the device (per state: each process's local
+ * transitions in order, then the synchronising actions), find-or-put as one
+ * batch, and the states reported new become the next frontier, in batch
+ * order.  Host arrays (may be NULL, else `levels` entries): batch_sizes[L]
+ * successors generated, new_counts[L] states new at level L, fop_ms[L] the
+ * find-or-put time (HIP events).  Allocates its buffers; synchronises. */
+int ht_bfs_explore(ht_table* t, const ht_bfs_model* model, uint64_t initial, uint32_t levels,
+                   uint64_t* batch_sizes, uint64_t* new_counts, double* fop_ms, hipStream_t stream);
+
 /* ---- serving: a request loop over resident tables ----------------------- */
 
 enum {

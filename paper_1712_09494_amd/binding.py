@@ -109,6 +109,42 @@ class HtServerStats(C.Structure):
         return {f: getattr(self, f) for f, _ in self._fields_}
 
 
+class HtBfsModel(C.Structure):
+    _fields_ = [
+        ("local_count", (C.c_uint8 * 16) * 16),
+        ("local_target", ((C.c_uint8 * 4) * 16) * 16),
+        ("sync_p", C.c_uint8 * 4),
+        ("sync_q", C.c_uint8 * 4),
+        ("sync_p_edge", (C.c_int8 * 16) * 4),
+        ("sync_q_edge", (C.c_int8 * 16) * 4),
+    ]
+
+
+def pack_bfs_model(model) -> HtBfsModel:
+    """ht_bfs_model from a model with .local[p][s] (target lists) and
+    .syncs[a] = (p, q, p_edges[s], q_edges[s]) (at most one edge each)."""
+    m = HtBfsModel()
+    for p in range(16):
+        for s in range(16):
+            ts = model.local[p][s]
+            if len(ts) > 4:
+                raise ValueError("at most 4 local transitions")
+            m.local_count[p][s] = len(ts)
+            for k, t in enumerate(ts):
+                m.local_target[p][s][k] = t
+    if len(model.syncs) != 4:
+        raise ValueError("exactly 4 synchronising actions")
+    for a, (sp, sq, pe, qe) in enumerate(model.syncs):
+        m.sync_p[a] = sp
+        m.sync_q[a] = sq
+        for s in range(16):
+            if len(pe[s]) > 1 or len(qe[s]) > 1:
+                raise ValueError("at most one synchronising edge per local state")
+            m.sync_p_edge[a][s] = pe[s][0] if pe[s] else -1
+            m.sync_q_edge[a][s] = qe[s][0] if qe[s] else -1
+    return m
+
+
 HT_OP_FIND_OR_PUT = 1
 HT_OP_QUERY = 2
 
@@ -162,6 +198,8 @@ _PROTOS = {
     "ht_reserve": (C.c_int, [_vp, _u64]),
     "ht_strerror": (C.c_char_p, [C.c_int]),
     "ht_last_error": (C.c_char_p, []),
+    "ht_bfs_explore": (C.c_int, [_vp, C.POINTER(HtBfsModel), _u64, _u32, C.POINTER(_u64), C.POINTER(_u64),
+                                 C.POINTER(C.c_double), _vp]),
     "ht_server_config_default": (None, [C.POINTER(HtServerConfig)]),
     "ht_server_create": (C.c_int, [C.POINTER(_vp), _u32, C.POINTER(HtServerConfig), C.POINTER(_vp)]),
     "ht_server_run": (C.c_int, [_vp, C.POINTER(HtRequest), _u32, C.POINTER(HtServerStats)]),
@@ -526,6 +564,22 @@ class Table:
 
     def reserve(self, max_batch: int) -> None:
         ht_reserve(self.handle, max_batch)
+
+    def bfs_explore(self, model, levels: int, initial: int = 0, stream=None) -> dict:
+        return ht_bfs_explore(self.handle, model, levels, initial, stream)
+
+
+def ht_bfs_explore(h: int, model, levels: int, initial: int = 0, stream=None) -> dict:
+    """Breadth-first exploration on the GPU with table h as the visited set."""
+    m = pack_bfs_model(model)
+    bs = (_u64 * max(levels, 1))()
+    nc = (_u64 * max(levels, 1))()
+    ms = (C.c_double * max(levels, 1))()
+    _check(load().ht_bfs_explore(h, C.byref(m), initial & EMPTY, levels, bs, nc, ms, _stream_handle(stream)),
+           "ht_bfs_explore")
+    done = [i for i in range(levels) if bs[i] or i == 0]
+    return {"batch_sizes": [int(bs[i]) for i in range(levels)], "new_counts": [int(nc[i]) for i in range(levels)],
+            "fop_ms": [float(ms[i]) for i in range(levels)], "levels": len(done)}
 
 
 class Server:

@@ -45,6 +45,12 @@ struct ht_table {
   uint32_t nscript = 0;
 };
 
+#define HT_HIP(call)                                           \
+  do {                                                         \
+    hipError_t e_ = (call);                                    \
+    if (e_ != hipSuccess) return ht_rt::hip_fail(e_, #call);   \
+  } while (0)
+
 namespace ht_rt {
 
 int fail(int code, const std::string& msg);

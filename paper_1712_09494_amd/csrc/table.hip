@@ -67,11 +67,6 @@ int hip_fail(hipError_t e, const char* what) {
   return HT_EHIP;
 }
 
-#define HT_HIP(call)                                   \
-  do {                                                 \
-    hipError_t e_ = (call);                            \
-    if (e_ != hipSuccess) return hip_fail(e_, #call);  \
-  } while (0)
 
 // Compute units of the current device (cached per device id).
 uint32_t device_cus(int dev) {

@@ -88,3 +88,18 @@ def test_missing_library_fails_loudly(tmp_path):
     finally:
         mod._lib = saved
     assert b2 is mod.load
+
+
+def test_bfs_model_packing():
+    from paper_1712_09494_amd import inputs
+    m = inputs.BfsModel(1)
+    pm = b.pack_bfs_model(m)
+    for p in range(16):
+        for s in range(16):
+            assert pm.local_count[p][s] == len(m.local[p][s])
+            assert list(pm.local_target[p][s])[: len(m.local[p][s])] == m.local[p][s]
+    for a, (sp, sq, pe, qe) in enumerate(m.syncs):
+        assert (pm.sync_p[a], pm.sync_q[a]) == (sp, sq)
+        assert [pm.sync_p_edge[a][s] for s in range(16)] == [x[0] if x else -1 for x in pe]
+    lib = b.load()
+    assert lib.ht_bfs_explore(None, C.byref(pm), 0, 3, None, None, None, None) == b.HT_EINVAL

@@ -254,12 +254,10 @@ def kernel_bytes(name, n, d_new, c, bucket_slots):
         lines = max(1, bucket_slots * 8 // LINE)
         return n * (9 + LINE * lines) + d_new * HALF
     if name == "cuckoo_probe":
-        # key + first slot line for keys found; all c slot lines + 16-byte list entry for misses;
-        # flag for hits
-        return n * 8 + (n - d_new) * (LINE + 1) + d_new * (c * LINE + 16)
-    if name == "cuckoo_place":
-        # list entry + compare-and-swap on one slot line (read + half-line write) + flag
-        return d_new * (16 + LINE + HALF + 1)
+        # key + flag + the h_1 slot line per key (the lookup stops at a hit or the
+        # first empty slot, so one line is the least any key reads); each new key's
+        # compare-and-swap dirties one half-line
+        return n * (9 + LINE) + d_new * HALF
     return None
 
 

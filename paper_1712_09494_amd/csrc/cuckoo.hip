@@ -25,49 +25,41 @@ hipError_t cuckoo_query(const DevTable& t, const uint64_t* keys, uint64_t n, uin
   return hipGetLastError();
 }
 
+// Kernel 1 of find-or-put: probe and place.
 hipError_t cuckoo_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
-                        const CuckooScratch& s, uint32_t grid, uint32_t R, bool scripted, hipStream_t st) {
-  if (scripted) {
-    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s);
+                        const CuckooScratch& s, uint32_t grid, uint32_t R, bool scripted, bool paper_order,
+                        hipStream_t st) {
+  if (scripted && paper_order) {
+    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s);
+  } else if (scripted) {
+    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s);
+  } else if (paper_order) {
+#define HT_P(RR) \
+  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s)
+    HT_R_DISPATCH(HT_P)
+#undef HT_P
   } else {
-#define HT_P(RR) hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s)
+#define HT_P(RR) \
+  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s)
     HT_R_DISPATCH(HT_P)
 #undef HT_P
   }
   return hipGetLastError();
 }
 
-// Phases 2-4 of find-or-put (phase 1 is cuckoo_probe).
-hipError_t cuckoo_place(const DevTable& t, uint64_t n, uint8_t* out, const CuckooScratch& s, uint32_t grid,
-                        uint32_t R, bool scripted, hipStream_t st) {
-  if (scripted) {
-    hipLaunchKernelGGL((cuckoo_place_kernel<1, true>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
-  } else {
-#define HT_PL(RR) hipLaunchKernelGGL((cuckoo_place_kernel<RR, false>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s)
-    HT_R_DISPATCH(HT_PL)
-#undef HT_PL
-  }
-  return hipGetLastError();
-}
-
+// Kernel 2: deduplicate the listed keys and run their eviction chains.
 hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const CuckooScratch& s, uint32_t grid,
-                        bool scripted, bool paper_order, hipStream_t st) {
-  if (scripted && paper_order)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<true, true>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
-  else if (scripted)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<true, false>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
-  else if (paper_order)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<false, true>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
+                        bool scripted, hipStream_t st) {
+  if (scripted)
+    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
   else
-    hipLaunchKernelGGL((cuckoo_evict_kernel<false, false>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
   return hipGetLastError();
 }
 
-hipError_t cuckoo_scrub(uint64_t n, const CuckooScratch& s, uint32_t grid, bool paper_order, hipStream_t st) {
-  if (paper_order)
-    hipLaunchKernelGGL((cuckoo_scrub_kernel<true>), dim3(grid), dim3(kBlock), 0, st, n, s);
-  else
-    hipLaunchKernelGGL((cuckoo_scrub_kernel<false>), dim3(grid), dim3(kBlock), 0, st, n, s);
+// Kernel 3: clear the scratch-set slots kernel 2 took.
+hipError_t cuckoo_scrub(uint64_t n, const CuckooScratch& s, uint32_t grid, hipStream_t st) {
+  hipLaunchKernelGGL(cuckoo_scrub_kernel, dim3(grid), dim3(kBlock), 0, st, n, s);
   return hipGetLastError();
 }
 

@@ -10,47 +10,73 @@
 // Duplicates (Sec. 5.1.1): the paper lets an inserter stop when it evicts its
 // own key.  That does not cover a key that is in flight -- evicted by one
 // lane and not yet re-placed -- while another lane looks it up, misses it and
-// inserts a second copy.  Here find-or-put runs in four kernels so that no
+// inserts a second copy.  Here find-or-put runs in three kernels so that no
 // lookup or duplicate check overlaps an eviction:
-//   1. probe: every key is looked up (read-only on the table); hits report 0;
-//      misses are listed with the mask of candidate slots h_j(k) seen empty.
-//   2. place: every miss compare-and-swaps itself into its candidate slots,
-//      in mask order.  No key moves in this phase and slots only go from
-//      empty to a key, so all copies of a key walk the same slots and meet:
-//      the first copy to reach an empty candidate wins and reports 1, the
-//      others find it there and report 0.  Misses that find every candidate
-//      taken are listed again.
-//   3. evict: the keys left over are deduplicated by compare-and-swap into a
+//   1. probe and place: every key is looked up in its c slots; a key that
+//      misses compare-and-swaps itself into the candidate slots it saw
+//      empty, in order h_1, h_2, ...  No key moves in this kernel and slots
+//      only go from empty to a key, so a later probe sees a subset of an
+//      earlier probe's empty slots and all copies of a key meet: the first
+//      copy to reach an empty candidate wins and reports 1, the others find
+//      it there (probe hit or compare-and-swap result) and report 0.  Keys
+//      that find every candidate taken are listed.
+//   2. evict: the listed keys are deduplicated by compare-and-swap into a
 //      scratch set (one winner per key) and the winners run the eviction
-//      chain of Sec. 4.1.  Exchanges conserve keys, so every key is in exactly
-//      one slot or held by exactly one lane.
-//   4. scrub: the winners' scratch-set slots are emptied again.
-// With the paper's insertion order (HT_FLAG_CUCKOO_PAPER_ORDER) phase 2 is
-// skipped and every miss goes through the scratch set and the chain, which
-// starts by exchanging the key into h_1.
+//      chain of Sec. 4.1.  Exchanges conserve keys, so every key is in
+//      exactly one slot or held by exactly one lane.
+//   3. scrub: the winners' scratch-set slots are emptied again.
+// With the paper's insertion order (HT_FLAG_CUCKOO_PAPER_ORDER) kernel 1
+// places nothing and lists every miss; its chain starts by exchanging the
+// key into h_1.
 // Lists are kept in per-wave regions of the scratch arrays (no global
-// counter); later phases walk the same regions and compact in place.  Only
-// the slots phase 3 used are cleared, so the set is empty for the next call
+// counter); later kernels walk the same regions.  Only the scratch-set slots
+// the evict kernel used are cleared, so the set is empty for the next call
 // without a fill pass.
 #pragma once
 #include "ht_device.h"
 
 namespace ht {
 
-// Look up R keys per lane in their c slots, probing h_1, h_2, ... with an
-// early exit on a hit; the loads of the R keys for one j are issued together.
-// hit[r] is set on a hit; empty_mask[r] gets bit j when slot h_j was empty.
+// Early exit on an empty slot.  Slots are never emptied (a key leaves a slot
+// only when an exchange puts another key there), a key is placed at h_j only
+// after h_1..h_{j-1} were seen taken, and a key evicted from h_j moves on to
+// h_{j+1} (or back to h_1).  So while a key's c slot indices are pairwise
+// distinct, a key stored at h_j has h_1..h_{j-1} all taken, and a lookup may
+// stop at the first empty slot of h_1, h_2, ...  A key with coinciding slot
+// indices can skip a slot when it is evicted (the next hash after the last
+// index that maps to its slot), so such keys always read all c slots.
+template <bool SCRIPTED>
+__device__ __forceinline__ bool hashes_distinct(const DevTable& t, uint64_t k) {
+  bool d = true;
+  for (uint32_t a = 0; a + 1 < t.nhash; ++a) {
+    const uint64_t ha = hidx<SCRIPTED>(t, k, a);
+    for (uint32_t b = a + 1; b < t.nhash; ++b) d &= hidx<SCRIPTED>(t, k, b) != ha;
+  }
+  return d;
+}
+
+template <int R>
+__device__ __forceinline__ bool any_lane(const bool (&f)[R]) {
+  bool a = false;
+#pragma unroll
+  for (int r = 0; r < R; ++r) a |= f[r];
+  return ballot(a) != 0;
+}
+
+// Look up R keys per lane in their c slots, probing h_1, h_2, ... and
+// stopping on a hit or (distinct indices) on an empty slot; the loads of the
+// R keys for one j are issued together.
 template <int R, bool SCRIPTED>
 __device__ __forceinline__ void cuckoo_lookup(const DevTable& t, const uint64_t (&k)[R], const bool (&live)[R],
-                                              bool (&hit)[R], uint32_t (&empty_mask)[R]) {
-  bool go[R];
+                                              bool (&hit)[R]) {
+  bool go[R], dist[R];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     hit[r] = false;
-    empty_mask[r] = 0;
     go[r] = live[r];
+    dist[r] = live[r] && hashes_distinct<SCRIPTED>(t, k[r]);
   }
-  for (uint32_t j = 0; j < t.nhash; ++j) {
+  for (uint32_t j = 0; j < t.nhash && any_lane(go); ++j) {
     uint64_t v[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) v[r] = go[r] ? t.slots[hidx<SCRIPTED>(t, k[r], j)] : kEmpty;
@@ -60,8 +86,8 @@ __device__ __forceinline__ void cuckoo_lookup(const DevTable& t, const uint64_t 
         if (v[r] == k[r]) {
           hit[r] = true;
           go[r] = false;
-        } else if (v[r] == kEmpty) {
-          empty_mask[r] |= 1u << j;
+        } else if (v[r] == kEmpty && dist[r]) {
+          go[r] = false;
         }
       }
     }
@@ -78,14 +104,13 @@ __global__ __launch_bounds__(kBlock) void cuckoo_query_kernel(DevTable t, const 
   for (uint64_t base = (uint64_t)blockIdx.x * per + threadIdx.x; base < n; base += stride) {
     uint64_t k[R];
     bool live[R], hit[R];
-    uint32_t em[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t i = base + (uint64_t)r * kBlock;
       k[r] = i < n ? keys[i] : kEmpty;
       live[r] = i < n && k[r] != kEmpty;
     }
-    cuckoo_lookup<R, SCRIPTED>(t, k, live, hit, em);
+    cuckoo_lookup<R, SCRIPTED>(t, k, live, hit);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t i = base + (uint64_t)r * kBlock;
@@ -99,10 +124,18 @@ __global__ __launch_bounds__(kBlock) void cuckoo_query_kernel(DevTable t, const 
   }
 }
 
-// Phase 1: lookup.  Wave w owns keys [w*per_wave, ...); a loop turn covers
-// 64*R keys, lane l taking base + r*64 + l.  Misses go to the wave's region
-// as (key, index | empty-candidate mask << 48).
-template <int R, bool SCRIPTED>
+constexpr uint64_t kIdxMask = (1ull << 40) - 1;
+
+// Kernel 1: probe and place.  Wave w owns keys [w*per_wave, ...); a loop
+// turn covers 64*R keys, lane l taking base + r*64 + l.  For j = 1..c each
+// pending key reads h_j: its own key there ends the search (found); an empty
+// slot is compare-and-swapped at once (placed, or found if another copy got
+// there first, or taken by another key: go on with h_{j+1}).  Keys whose
+// slot indices coincide read all c slots first and then try the empty ones
+// in order.  Keys with every candidate taken go to the wave's region as
+// (key, index).  In paper order nothing is placed: the first empty slot (or
+// the end of the probe) lists the key.
+template <int R, bool SCRIPTED, bool PAPER_ORDER>
 __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable& t, const uint64_t* __restrict__ keys,
                                                                   uint64_t n, uint8_t* __restrict__ out,
                                                                   const CuckooScratch& s, uint64_t wave) {
@@ -112,52 +145,131 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
   if (end > n) end = n;
   const uint32_t sc = t.ctr->stash_count;
   const uint32_t oc = t.ctr->overflow_count;
-  uint32_t nmiss = 0;
-  unsigned long long nsent = 0;
+  uint32_t nlist = 0;
+  unsigned long long nnew = 0;
   for (uint64_t base = begin; base < end; base += (uint64_t)kWave * R) {
     uint64_t k[R];
-    bool act[R], live[R], hit[R];
+    bool act[R], pend[R], dist[R], lst[R];
     uint32_t em[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t i = base + (uint64_t)r * kWave + lane;
       act[r] = i < end;
       k[r] = act[r] ? keys[i] : 0;
-      live[r] = act[r] && k[r] != kEmpty;
+      pend[r] = act[r] && k[r] != kEmpty;
+      dist[r] = pend[r] && hashes_distinct<SCRIPTED>(t, k[r]);
+      lst[r] = false;
+      em[r] = 0;
     }
-    cuckoo_lookup<R, SCRIPTED>(t, k, live, hit, em);
 #pragma unroll
     for (int r = 0; r < R; ++r) {
-      const uint64_t i = base + (uint64_t)r * kWave + lane;
-      uint32_t res = 0;
       // the all-ones key: one lane per wave competes for the flag word
       const uint64_t sent = ballot(act[r] && k[r] == kEmpty);
-      if (sent && lane == (int)__builtin_ctzll(sent)) {
-        res = sentinel_put(t);
-        nsent += res;
+      if (act[r] && k[r] == kEmpty) {
+        uint32_t res = 0;
+        if (lane == (int)__builtin_ctzll(sent)) {
+          res = sentinel_put(t);
+          nnew += res;
+        }
+        if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
       }
-      if (live[r] && !hit[r] && (sc | oc)) hit[r] = stash_query(t, k[r], sc, oc);
-      const bool miss = live[r] && !hit[r];
-      if (act[r] && !miss && out) out[i] = (uint8_t)res;
-      const uint64_t mm = ballot(miss);
-      if (miss) {
-        const uint64_t slot = begin + nmiss + lanes_below(mm);
+      // keys in the stash or the overflow list are found before any placement
+      if (pend[r] && (sc | oc) && stash_query(t, k[r], sc, oc)) {
+        if (out) out[base + (uint64_t)r * kWave + lane] = 0;
+        pend[r] = false;
+      }
+    }
+    for (uint32_t j = 0; j < t.nhash && any_lane(pend); ++j) {
+      uint64_t idx[R], v[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        idx[r] = pend[r] ? hidx<SCRIPTED>(t, k[r], j) : 0;
+        v[r] = pend[r] ? t.slots[idx[r]] : 0;
+      }
+      bool cas[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        cas[r] = false;
+        if (!pend[r]) continue;
+        if (v[r] == k[r]) {
+          if (out) out[base + (uint64_t)r * kWave + lane] = 0;
+          pend[r] = false;
+        } else if (v[r] == kEmpty) {
+          if (!dist[r]) {
+            em[r] |= 1u << j;
+          } else if (PAPER_ORDER) {
+            lst[r] = true;
+            pend[r] = false;
+          } else {
+            cas[r] = true;
+          }
+        }
+      }
+      if (PAPER_ORDER) continue;
+      uint64_t old[R];
+#pragma unroll
+      for (int r = 0; r < R; ++r) old[r] = cas[r] ? cas64(&t.slots[idx[r]], kEmpty, k[r]) : 0;
+#pragma unroll
+      for (int r = 0; r < R; ++r) {
+        if (cas[r] && (old[r] == kEmpty || old[r] == k[r])) {
+          const uint32_t res = old[r] == kEmpty ? 1u : 0u;   // placed, or another copy was
+          nnew += res;
+          if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
+          pend[r] = false;
+        }
+      }
+    }
+    // keys with coinciding slot indices: try the empty candidates in order
+    if (!PAPER_ORDER) {
+      for (;;) {
+        bool go[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) go[r] = pend[r] && em[r];
+        if (!any_lane(go)) break;
+        uint64_t old[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          old[r] = 0;
+          if (go[r]) {
+            const uint32_t j = (uint32_t)__builtin_ctz(em[r]);
+            em[r] &= em[r] - 1;
+            old[r] = cas64(&t.slots[hidx<SCRIPTED>(t, k[r], j)], kEmpty, k[r]);
+          }
+        }
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if (go[r] && (old[r] == kEmpty || old[r] == k[r])) {
+            const uint32_t res = old[r] == kEmpty ? 1u : 0u;
+            nnew += res;
+            if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
+            pend[r] = false;
+          }
+        }
+      }
+    }
+    // every candidate taken (or, in paper order, not found): list for the evict kernel
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+      const bool l = pend[r] || lst[r];
+      const uint64_t mm = ballot(l);
+      if (l) {
+        const uint64_t slot = begin + nlist + lanes_below(mm);
         s.wkey[slot] = k[r];
-        s.wmeta[slot] = i | ((uint64_t)em[r] << 48);
+        s.wmeta[slot] = base + (uint64_t)r * kWave + lane;
       }
-      nmiss += (uint32_t)__popcll(mm);
+      nlist += (uint32_t)__popcll(mm);
     }
   }
-  if (lane == 0 && begin < n) s.wcnt[wave] = nmiss;
-  return nsent;
+  if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
+  return nnew;
 }
 
-template <int R, bool SCRIPTED>
+template <int R, bool SCRIPTED, bool PAPER_ORDER>
 __global__ __launch_bounds__(kBlock) void cuckoo_probe_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                                uint64_t n, uint8_t* __restrict__ out,
                                                                CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  wave_count(t.ctr->size, cuckoo_probe_region<R, SCRIPTED>(t, keys, n, out, s, wave), (uint32_t)wave);
+  wave_count(t.ctr->size, cuckoo_probe_region<R, SCRIPTED, PAPER_ORDER>(t, keys, n, out, s, wave), (uint32_t)wave);
 }
 
 // Eviction chain of Sec. 4.1 for key x starting at slot index `slot` (which
@@ -192,93 +304,15 @@ __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uin
   }
 }
 
-constexpr uint64_t kIdxMask = (1ull << 40) - 1;
-
-// Phase 2: place.  Wave w walks the misses of its region, R per lane per
-// turn, compare-and-swapping each into its empty candidates (all R issued
-// together).  Keys that find every candidate taken are compacted to the
-// front of the region for phase 3.
-template <int R, bool SCRIPTED>
-__device__ __forceinline__ unsigned long long cuckoo_place_region(const DevTable& t, uint64_t n,
-                                                                  uint8_t* __restrict__ out, const CuckooScratch& s,
-                                                                  uint64_t wave) {
-  const int lane = lane_id();
-  const uint64_t begin = wave * s.per_wave;
-  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
-  unsigned long long nnew = 0;
-  uint32_t nleft = 0;
-  for (uint32_t e0 = 0; e0 < cnt; e0 += kWave * R) {
-    uint64_t x[R], meta[R];
-    bool live[R], done[R];
-    uint32_t em[R];
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const uint32_t e = e0 + r * kWave + lane;
-      live[r] = e < cnt;
-      x[r] = live[r] ? s.wkey[begin + e] : 0;
-      meta[r] = live[r] ? s.wmeta[begin + e] : 0;
-      done[r] = !live[r];
-      em[r] = (uint32_t)(meta[r] >> 48);
-    }
-    for (;;) {
-      bool any = false;
-#pragma unroll
-      for (int r = 0; r < R; ++r) any |= !done[r] && em[r];
-      if (!any) break;
-      uint64_t old[R];
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        old[r] = 0;
-        if (!done[r] && em[r]) {
-          const uint32_t j = (uint32_t)__builtin_ctz(em[r]);
-          em[r] &= em[r] - 1;
-          old[r] = cas64(&t.slots[hidx<SCRIPTED>(t, x[r], j)], kEmpty, x[r]);
-        }
-      }
-#pragma unroll
-      for (int r = 0; r < R; ++r) {
-        if (!done[r] && (old[r] == kEmpty || old[r] == x[r])) {
-          const uint32_t res = old[r] == kEmpty ? 1u : 0u;   // placed, or another copy was
-          nnew += res;
-          if (out) out[meta[r] & kIdxMask] = (uint8_t)res;
-          done[r] = true;
-        }
-      }
-    }
-    // every candidate taken: keep for the eviction phase (in-place compaction)
-#pragma unroll
-    for (int r = 0; r < R; ++r) {
-      const bool left = !done[r];
-      const uint64_t lm = ballot(left);
-      if (left) {
-        const uint64_t slot = begin + nleft + lanes_below(lm);
-        s.wkey[slot] = x[r];
-        s.wmeta[slot] = meta[r];
-      }
-      nleft += (uint32_t)__popcll(lm);
-    }
-  }
-  if (lane == 0 && begin < n) s.ccnt[wave] = nleft;
-  return nnew;
-}
-
-template <int R, bool SCRIPTED>
-__global__ __launch_bounds__(kBlock) void cuckoo_place_kernel(DevTable t, uint64_t n, uint8_t* __restrict__ out,
-                                                               CuckooScratch s) {
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  wave_count(t.ctr->size, cuckoo_place_region<R, SCRIPTED>(t, n, out, s, wave), (uint32_t)wave);
-}
-
-// Phase 3: evict.  The keys left by phase 2 (or, in paper order, every
-// miss) are deduplicated in the scratch set; each winner reports 1 and runs
-// the eviction chain from h_1.
-template <bool SCRIPTED, bool PAPER_ORDER>
+// Kernel 2: evict.  The keys kernel 1 listed are deduplicated in the
+// scratch set; each winner reports 1 and runs the eviction chain from h_1.
+template <bool SCRIPTED>
 __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
                                                     const CuckooScratch& s, uint64_t wave,
                                                     unsigned long long& nnew, unsigned long long& nevict) {
   const int lane = lane_id();
   const uint64_t begin = wave * s.per_wave;
-  const uint32_t cnt = begin < n ? (PAPER_ORDER ? s.wcnt[wave] : s.ccnt[wave]) : 0u;
+  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
   for (uint32_t e = lane; e < cnt; e += kWave) {
     const uint64_t k = s.wkey[begin + e];
     const uint64_t meta = s.wmeta[begin + e];
@@ -291,7 +325,7 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
       p = (p + 1) & s.dset_mask;
     }
     if (out) out[meta & kIdxMask] = winner ? 1 : 0;
-    // remember the scratch-set slot for phase 4 (~0: nothing to clear)
+    // remember the scratch-set slot for the scrub kernel (~0: nothing to clear)
     s.wmeta[begin + e] = winner ? p : ~0ull;
     if (!winner) continue;
     uint64_t y = k;
@@ -301,33 +335,31 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
   }
 }
 
-template <bool SCRIPTED, bool PAPER_ORDER>
+template <bool SCRIPTED>
 __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64_t n, uint8_t* __restrict__ out,
                                                                CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   unsigned long long nnew = 0, nevict = 0;
-  cuckoo_evict_region<SCRIPTED, PAPER_ORDER>(t, n, out, s, wave, nnew, nevict);
+  cuckoo_evict_region<SCRIPTED>(t, n, out, s, wave, nnew, nevict);
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
 }
 
-// Phase 4: empty the scratch-set slots the winners of phase 3 took.  It runs
-// after phase 3 has finished, so no copy of a key can find its slot empty and
-// win a second time.
-template <bool PAPER_ORDER>
+// Kernel 3: empty the scratch-set slots the winners of kernel 2 took.  It
+// runs after kernel 2 has finished, so no copy of a key can find its slot
+// empty and win a second time.
 __device__ __forceinline__ void cuckoo_scrub_region(uint64_t n, const CuckooScratch& s, uint64_t wave) {
   const int lane = lane_id();
   const uint64_t begin = wave * s.per_wave;
-  const uint32_t cnt = begin < n ? (PAPER_ORDER ? s.wcnt[wave] : s.ccnt[wave]) : 0u;
+  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
   for (uint32_t e = lane; e < cnt; e += kWave) {
     const uint64_t p = s.wmeta[begin + e];
     if (p != ~0ull) s.dset[p] = kEmpty;
   }
 }
 
-template <bool PAPER_ORDER>
 __global__ __launch_bounds__(kBlock) void cuckoo_scrub_kernel(uint64_t n, CuckooScratch s) {
-  cuckoo_scrub_region<PAPER_ORDER>(n, s, ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
+  cuckoo_scrub_region(n, s, ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
 }
 
 }  // namespace ht

@@ -88,9 +88,8 @@ struct CuckooScratch {
   uint64_t dset_mask;
   uint64_t dset_seed;
   uint64_t* wkey;        // listed keys, per-wave regions
-  uint64_t* wmeta;       // key index | empty-candidate mask << 48 (scratch-set slot after phase 3)
-  uint32_t* wcnt;        // misses per wave (phase 1)
-  uint32_t* ccnt;        // keys left for the eviction phase per wave (phase 2)
+  uint64_t* wmeta;       // key index (scratch-set slot once the evict kernel has run)
+  uint32_t* wcnt;        // listed keys per wave
   uint64_t per_wave;     // keys (and list room) per wave
 };
 

@@ -22,12 +22,9 @@ uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R);
 hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
                         hipStream_t);
 hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
-                        uint32_t, bool, hipStream_t);
-hipError_t cuckoo_place(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t, bool,
-                        hipStream_t);
-hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, bool,
-                        hipStream_t);
-hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, bool, hipStream_t);
+                        uint32_t, bool, bool, hipStream_t);
+hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, hipStream_t);
+hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, hipStream_t);
 hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
@@ -236,7 +233,7 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   const uint64_t nw = (uint64_t)max_blocks(t) * (kBlock / kWave);
   const size_t b_dset = align_up(ds * 8, 256);
   const size_t b_k = align_up(n * 8, 256);
-  const size_t b_c = align_up(2 * nw * 4, 256);   // wcnt and ccnt
+  const size_t b_c = align_up(nw * 4, 256);   // wcnt
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c);
   if (e != hipSuccess) {
@@ -358,7 +355,6 @@ CuckooScratch scratch_view(const ht_table* t, uint64_t n) {
   sc.wkey = t->wkey;
   sc.wmeta = t->wmeta;
   sc.wcnt = t->wcnt;
-  sc.ccnt = t->wcnt + (uint64_t)max_blocks(t) * (kBlock / kWave);
   return sc;
 }
 
@@ -382,22 +378,18 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
   const uint64_t nwaves = blocks * 4;
   CuckooScratch sc = scratch_view(t, n);
   sc.per_wave = (n + nwaves - 1) / nwaves;
+  const bool paper = (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
   {
     KernelTimer kt("cuckoo_probe", s);
-    HT_HIP(cuckoo_probe(d, keys, n, out, sc, (uint32_t)blocks, R, scripted, s));
-  }
-  const bool paper = (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
-  if (!paper) {
-    KernelTimer kt("cuckoo_place", s);
-    HT_HIP(cuckoo_place(d, n, out, sc, (uint32_t)blocks, R, scripted, s));
+    HT_HIP(cuckoo_probe(d, keys, n, out, sc, (uint32_t)blocks, R, scripted, paper, s));
   }
   {
     KernelTimer kt("cuckoo_evict", s);
-    HT_HIP(cuckoo_evict(d, n, out, sc, (uint32_t)blocks, scripted, paper, s));
+    HT_HIP(cuckoo_evict(d, n, out, sc, (uint32_t)blocks, scripted, s));
   }
   {
     KernelTimer kt("cuckoo_scrub", s);
-    HT_HIP(cuckoo_scrub(n, sc, (uint32_t)blocks, paper, s));
+    HT_HIP(cuckoo_scrub(n, sc, (uint32_t)blocks, s));
   }
   return HT_OK;
 }

@@ -79,10 +79,42 @@ def test_cuckoo_key_in_candidate_slot_or_stash(flags):
     pos = {int(k): i for i, k in enumerate(slots.tolist()) if k != E}
     assert len(pos) + len(stash) == n
     for k in keys[:5000].tolist():
+        hs = [t.hash_index(k, j) for j in range(3)]
         if k in pos:
-            assert pos[k] in [t.hash_index(k, j) for j in range(3)]
+            assert pos[k] in hs
+            # the lookup stops at the first empty slot: every slot before the
+            # key's own in h_1, h_2, ... must be taken (distinct indices)
+            if len(set(hs)) == 3:
+                j = hs.index(pos[k])
+                assert all(slots[h] != E for h in hs[:j]), (k, hs, j)
         else:
             assert k in stash
+    t.close()
+
+
+@pytest.mark.parametrize("flags", [0, b.HT_FLAG_CUCKOO_PAPER_ORDER])
+def test_cuckoo_coinciding_indices_keep_full_lookup(flags):
+    """A key with h_1 == h_3 (c = 4) evicted from that slot skips h_2 and moves
+    to h_4 (next hash after the last index mapping to its slot, Sec. 4.1),
+    leaving h_2 empty; find-or-put of it again must still find it."""
+    y, x, f5, f6, f7 = 1001, 3000, 2005, 2006, 2007
+    script = {y: [0, 1, 0, 2], f5: [5, 8, 9, 10], f6: [6, 11, 12, 13], f7: [7, 14, 15, 16],
+              x: [0, 5, 6, 7]}
+    t = b.Table("cuckoo", capacity=64, nhash=4, flags=flags | b.HT_FLAG_SCRIPTED_HASH)
+    t.set_scripted_hash(script)
+
+    def fop(ks):
+        return b.u64(t.find_or_put(dev(np.array(ks, dtype=np.uint64))).to(torch.int64)).tolist()
+
+    assert fop([y]) == [1]
+    assert fop([f5, f6, f7]) == [1, 1, 1]
+    assert fop([x]) == [1]
+    r = raw(t)[:64]
+    assert positions(r) == {x: 0, y: 2, f5: 5, f6: 6, f7: 7}
+    assert r[1] == E
+    assert fop([y, y, x]) == [0, 0, 0]
+    assert b.u64(t.query(dev(np.array([y, x, 4242], dtype=np.uint64))).to(torch.int64)).tolist() == [1, 1, 0]
+    assert t.size() == 5 and positions(raw(t)[:64]) == {x: 0, y: 2, f5: 5, f6: 6, f7: 7}
     t.close()
 
 

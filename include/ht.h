@@ -161,8 +161,9 @@ int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n,
  * pointers themselves are device pointers; a flag pointer may be NULL).
  * Tables may mix kinds, bucket sizes and hash counts; each table may appear
  * at most once; scripted-hash tables are rejected.  All bucketed tables are
- * served by one persistent kernel; each Cuckoo table then runs its own phase
- * kernels on the same stream.  Results equal one ht_find_or_put per table.
+ * served by one persistent kernel; all Cuckoo tables then run their three
+ * phases (probe and place, evict, scrub) as three launches over all of them,
+ * on the same stream.  Results equal one ht_find_or_put per table.
  * Builds a plan (allocating), launches it and synchronises `stream`. */
 int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
@@ -178,8 +179,8 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
                          uint32_t ntables, ht_multi_plan** out);
 
-/* Run the plan on `stream`: a small reset kernel and one persistent kernel
- * for the bucketed tables, then the phase kernels of each Cuckoo table.
+/* Run the plan on `stream`: one persistent kernel for the bucketed tables,
+ * then three phase kernels covering every Cuckoo table.
  * Allocates nothing, uses no memset and does not synchronise, so it may be
  * captured in a HIP graph and replayed.  Launches of one plan, and calls on
  * its tables, must be ordered on one stream. */

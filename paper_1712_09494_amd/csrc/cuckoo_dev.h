@@ -358,8 +358,4 @@ __device__ __forceinline__ void cuckoo_scrub_region(uint64_t n, const CuckooScra
   }
 }
 
-__global__ __launch_bounds__(kBlock) void cuckoo_scrub_kernel(uint64_t n, CuckooScratch s) {
-  cuckoo_scrub_region(n, s, ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave);
-}
-
 }  // namespace ht

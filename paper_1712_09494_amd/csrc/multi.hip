@@ -14,13 +14,17 @@
 // find-or-put call per table.  The launch allocates nothing and uses no
 // memset, so it can be captured in a HIP graph.
 //
-// Cuckoo tables of a many-table call run their four phase kernels per table
-// after this kernel, in the same stream order (see the host runtime): their
-// phases need a grid-wide barrier between them, which kernel boundaries give.
+// The Cuckoo tables of a many-table call run their three phases (probe and
+// place, evict, scrub) as three launches over all of them: the phases need a
+// grid-wide barrier between them, which kernel boundaries give.  Each launch
+// walks the same item list (table, region); a region is the part of a table's
+// batch whose misses one wave lists, exactly as in the single-table kernels.
+#include <algorithm>
 #include <cstring>
 #include <vector>
 
 #include "bucketed_dev.h"
+#include "cuckoo_dev.h"
 #include "multi.h"
 
 namespace ht {
@@ -59,6 +63,65 @@ __global__ __launch_bounds__(kBlock) void multi_fill_kernel(const MultiTable* __
   }
 }
 
+struct MultiCuckoo {
+  DevTable t;
+  CuckooScratch s;          // per_wave = keys per region
+  const uint64_t* keys;
+  uint8_t* out;
+  uint64_t n;
+  uint32_t paper;           // HT_FLAG_CUCKOO_PAPER_ORDER
+  uint32_t pad_;
+};
+
+__device__ __forceinline__ uint64_t uniform_item(const uint64_t* items, uint64_t idx) {
+  const uint64_t raw = items[idx];
+  return ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(raw >> 32)) << 32) |
+         __builtin_amdgcn_readfirstlane((uint32_t)raw);
+}
+
+__global__ __launch_bounds__(kBlock) void multi_cuckoo_probe_kernel(const MultiCuckoo* __restrict__ tabs,
+                                                                    const uint64_t* __restrict__ items,
+                                                                    uint32_t nitems) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t idx = wave; idx < nitems; idx += nwaves) {
+    const uint64_t it = uniform_item(items, idx);
+    const MultiCuckoo& m = tabs[(uint32_t)(it >> 40)];
+    const uint64_t region = it & kRegionMask;
+    const unsigned long long nnew =
+        m.paper ? cuckoo_probe_region<1, false, true>(m.t, m.keys, m.n, m.out, m.s, region)
+                : cuckoo_probe_region<1, false, false>(m.t, m.keys, m.n, m.out, m.s, region);
+    wave_count(m.t.ctr->size, nnew, (uint32_t)(wave + idx));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void multi_cuckoo_evict_kernel(const MultiCuckoo* __restrict__ tabs,
+                                                                    const uint64_t* __restrict__ items,
+                                                                    uint32_t nitems) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t idx = wave; idx < nitems; idx += nwaves) {
+    const uint64_t it = uniform_item(items, idx);
+    const MultiCuckoo& m = tabs[(uint32_t)(it >> 40)];
+    unsigned long long nnew = 0, nevict = 0;
+    cuckoo_evict_region<false>(m.t, m.n, m.out, m.s, it & kRegionMask, nnew, nevict);
+    wave_count(m.t.ctr->size, nnew, (uint32_t)(wave + idx));
+    wave_count(m.t.ctr->evictions, nevict, (uint32_t)(wave + idx));
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void multi_cuckoo_scrub_kernel(const MultiCuckoo* __restrict__ tabs,
+                                                                    const uint64_t* __restrict__ items,
+                                                                    uint32_t nitems) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  for (uint64_t idx = wave; idx < nitems; idx += nwaves) {
+    const uint64_t it = uniform_item(items, idx);
+    const MultiCuckoo& m = tabs[(uint32_t)(it >> 40)];
+    cuckoo_scrub_region(m.n, m.s, it & kRegionMask);
+  }
+}
+
 // Item size for a launch of `total` keys on a device with `max_waves` wave
 // slots: a power of two in [256, 4096] giving about max_waves items.
 uint64_t multi_chunk(uint64_t total, uint64_t max_waves) {
@@ -74,25 +137,21 @@ uint32_t multi_grid(uint64_t nitems, uint32_t max_blocks) {
 
 // ---- host side ------------------------------------------------------------
 
-struct MultiPlanDev {
-  MultiTable* tabs = nullptr;
-  uint64_t* items = nullptr;
-  unsigned int* ctl = nullptr;
-  void* base = nullptr;
-  uint32_t nitems = 0;
-  uint32_t nctl = 0;
-  uint32_t grid = 0;
-};
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
-// Build descriptors and the item queue on the host and copy them to one
-// device allocation (synchronous).  Returns hipSuccess or the HIP error.
-hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, uint32_t max_blocks, MultiPlanDev& plan) {
+// Build descriptors and the item lists on the host and copy them to one
+// device allocation (synchronous).  Returns hipSuccess or the HIP error
+// (hipErrorInvalidValue when a Cuckoo table's scratch has too few per-wave
+// counts for its regions).
+hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, const std::vector<MultiCuckooSpec>& cspecs,
+                            uint32_t max_blocks, MultiPlanDev& plan) {
+  const uint64_t max_waves = (uint64_t)max_blocks * (kBlock / kWave);
   const uint32_t nt = (uint32_t)specs.size();
   std::vector<MultiTable> tabs(nt);
   std::vector<uint64_t> items;
   uint64_t total = 0;
   for (const auto& sp : specs) total += sp.n;
-  const uint64_t chunk = multi_chunk(total, (uint64_t)max_blocks * (kBlock / kWave));
+  const uint64_t chunk = multi_chunk(total, max_waves);
   for (uint32_t i = 0; i < nt; ++i) {
     const MultiSpec& sp = specs[i];
     MultiTable& m = tabs[i];
@@ -105,21 +164,52 @@ hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, uint32_t max_bl
     m.nregions = sp.n ? (uint32_t)((sp.n + m.chunk - 1) / m.chunk) : 0;
     for (uint64_t r = 0; r < m.nregions; ++r) items.push_back(make_item(i, r));
   }
+  // Cuckoo: one region per wave of 64 keys at least; a table never has more
+  // regions than its scratch has per-wave counts
+  const uint32_t nc = (uint32_t)cspecs.size();
+  std::vector<MultiCuckoo> ctabs(nc);
+  std::vector<uint64_t> citems;
+  uint64_t ctotal = 0;
+  for (const auto& sp : cspecs) ctotal += sp.n;
+  const uint64_t cchunk = multi_chunk(ctotal, max_waves);
+  for (uint32_t i = 0; i < nc; ++i) {
+    const MultiCuckooSpec& sp = cspecs[i];
+    MultiCuckoo& m = ctabs[i];
+    std::memset(&m, 0, sizeof(m));
+    m.t = sp.t;
+    m.s = sp.s;
+    m.keys = sp.keys;
+    m.out = sp.out;
+    m.n = sp.n;
+    m.paper = sp.paper ? 1u : 0u;
+    uint64_t per = std::max<uint64_t>(cchunk, (sp.n + sp.max_regions - 1) / std::max<uint64_t>(sp.max_regions, 1));
+    per = (per + kWave - 1) / kWave * kWave;
+    m.s.per_wave = per;
+    const uint64_t nr = sp.n ? (sp.n + per - 1) / per : 0;
+    if (nr > sp.max_regions) return hipErrorInvalidValue;
+    for (uint64_t r = 0; r < nr; ++r) citems.push_back(make_item(i, r));
+  }
   plan.nitems = (uint32_t)items.size();
+  plan.ncitems = (uint32_t)citems.size();
   plan.grid = multi_grid(plan.nitems, max_blocks);
-  plan.nctl = 0;
-  const size_t b_tabs = (sizeof(MultiTable) * nt + 255) / 256 * 256;
-  const size_t b_items = (items.size() * 8 + 255) / 256 * 256;
-  const size_t b_ctl = 256;
-  hipError_t e = hipMalloc(&plan.base, b_tabs + b_items + b_ctl);
+  plan.cgrid = multi_grid(plan.ncitems, max_blocks);
+  const size_t b_tabs = align256(sizeof(MultiTable) * nt);
+  const size_t b_items = align256(items.size() * 8);
+  const size_t b_ctabs = align256(sizeof(MultiCuckoo) * nc);
+  const size_t b_citems = align256(citems.size() * 8);
+  hipError_t e = hipMalloc(&plan.base, b_tabs + b_items + b_ctabs + b_citems + 256);
   if (e != hipSuccess) return e;
   char* c = static_cast<char*>(plan.base);
   plan.tabs = reinterpret_cast<MultiTable*>(c);
   plan.items = reinterpret_cast<uint64_t*>(c + b_tabs);
-  plan.ctl = reinterpret_cast<unsigned int*>(c + b_tabs + b_items);
+  plan.ctabs = reinterpret_cast<MultiCuckoo*>(c + b_tabs + b_items);
+  plan.citems = reinterpret_cast<uint64_t*>(c + b_tabs + b_items + b_ctabs);
   if (nt) e = hipMemcpy(plan.tabs, tabs.data(), sizeof(MultiTable) * nt, hipMemcpyHostToDevice);
   if (e == hipSuccess && !items.empty())
     e = hipMemcpy(plan.items, items.data(), items.size() * 8, hipMemcpyHostToDevice);
+  if (e == hipSuccess && nc) e = hipMemcpy(plan.ctabs, ctabs.data(), sizeof(MultiCuckoo) * nc, hipMemcpyHostToDevice);
+  if (e == hipSuccess && !citems.empty())
+    e = hipMemcpy(plan.citems, citems.data(), citems.size() * 8, hipMemcpyHostToDevice);
   return e;
 }
 
@@ -131,6 +221,19 @@ void multi_plan_free(MultiPlanDev& plan) {
 hipError_t multi_plan_launch(const MultiPlanDev& plan, hipStream_t s) {
   if (plan.nitems == 0) return hipSuccess;
   hipLaunchKernelGGL(multi_fill_kernel, dim3(plan.grid), dim3(kBlock), 0, s, plan.tabs, plan.items, plan.nitems);
+  return hipGetLastError();
+}
+
+// The Cuckoo phases: `phase` 0 = probe and place, 1 = evict, 2 = scrub.
+hipError_t multi_cuckoo_launch(const MultiPlanDev& plan, int phase, hipStream_t s) {
+  if (plan.ncitems == 0) return hipSuccess;
+  const dim3 g(plan.cgrid), b(kBlock);
+  if (phase == 0)
+    hipLaunchKernelGGL(multi_cuckoo_probe_kernel, g, b, 0, s, plan.ctabs, plan.citems, plan.ncitems);
+  else if (phase == 1)
+    hipLaunchKernelGGL(multi_cuckoo_evict_kernel, g, b, 0, s, plan.ctabs, plan.citems, plan.ncitems);
+  else
+    hipLaunchKernelGGL(multi_cuckoo_scrub_kernel, g, b, 0, s, plan.ctabs, plan.citems, plan.ncitems);
   return hipGetLastError();
 }
 
@@ -146,14 +249,13 @@ hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items) {
   d.cap_items = cap_items;
   const size_t b_tabs = (sizeof(MultiTable) * cap_tabs + 255) / 256 * 256;
   const size_t b_items = ((size_t)cap_items * 8 + 255) / 256 * 256;
-  hipError_t e = hipMalloc(&d.d_base, b_tabs + b_items + 256);
+  hipError_t e = hipMalloc(&d.d_base, b_tabs + b_items);
   if (e != hipSuccess) return e;
   e = hipHostMalloc(&d.h_base, b_tabs + b_items, hipHostMallocDefault);
   if (e != hipSuccess) return e;
   char* c = static_cast<char*>(d.d_base);
   d.d_tabs = reinterpret_cast<MultiTable*>(c);
   d.d_items = reinterpret_cast<uint64_t*>(c + b_tabs);
-  d.d_ctl = reinterpret_cast<unsigned int*>(c + b_tabs + b_items);
   char* h = static_cast<char*>(d.h_base);
   d.h_tabs = reinterpret_cast<MultiTable*>(h);
   d.h_items = reinterpret_cast<uint64_t*>(h + b_tabs);

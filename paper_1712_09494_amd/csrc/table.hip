@@ -29,18 +29,6 @@ hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                          hipStream_t);
-struct MultiPlanDev {
-  MultiTable* tabs = nullptr;
-  uint64_t* items = nullptr;
-  unsigned int* ctl = nullptr;
-  void* base = nullptr;
-  uint32_t nitems = 0;
-  uint32_t nctl = 0;
-  uint32_t grid = 0;
-};
-hipError_t multi_plan_build(const std::vector<MultiSpec>&, uint32_t, MultiPlanDev&);
-void multi_plan_free(MultiPlanDev&);
-hipError_t multi_plan_launch(const MultiPlanDev&, hipStream_t);
 hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_t);
 hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
                         hipStream_t);
@@ -146,14 +134,7 @@ void resolve_timings() {
 
 struct ht_multi_plan {
   std::vector<ht_table*> tables;
-  MultiPlanDev dev;           // the bucketed tables' persistent launch
-  struct CuckooJob {
-    ht_table* t;
-    const uint64_t* keys;
-    uint8_t* out;
-    uint64_t n;
-  };
-  std::vector<CuckooJob> cuckoo;   // run with their own phase kernels
+  MultiPlanDev dev;           // bucketed persistent launch + Cuckoo phase launches
   uint32_t grid = 0;
 };
 
@@ -539,7 +520,7 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
   if (ntables && (!t || !d_keys || !n || !d_out_is_new)) return fail(HT_EINVAL, "NULL argument array");
   if (ntables > (1u << 23)) return fail(HT_EINVAL, "too many tables in one plan");
   std::vector<MultiSpec> specs;
-  std::vector<ht_multi_plan::CuckooJob> cuckoo;
+  std::vector<MultiCuckooSpec> cuckoo;
   std::vector<ht_table*> seen;
   for (uint32_t i = 0; i < ntables; ++i) {
     int rc = check_table(t[i]);
@@ -553,7 +534,17 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
     if (t[i]->cfg.kind == HT_CUCKOO) {
       rc = reserve_scratch(t[i], n[i]);     // so that launches allocate nothing
       if (rc) return rc;
-      if (n[i]) cuckoo.push_back({t[i], d_keys[i], d_out_is_new[i], n[i]});
+      if (n[i]) {
+        MultiCuckooSpec cs{};
+        cs.t = launch_view(t[i]);
+        cs.s = scratch_view(t[i], n[i]);
+        cs.keys = d_keys[i];
+        cs.out = d_out_is_new[i];
+        cs.n = n[i];
+        cs.max_regions = (uint64_t)max_blocks(t[i]) * (kBlock / kWave);
+        cs.paper = (t[i]->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
+        cuckoo.push_back(cs);
+      }
       continue;
     }
     MultiSpec sp{};
@@ -565,11 +556,10 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
   }
   ht_multi_plan* p = new ht_multi_plan();
   p->tables = seen;
-  p->cuckoo = cuckoo;
   int dev = 0;
   (void)hipGetDevice(&dev);
   p->grid = device_cus(dev) * 8;
-  hipError_t e = multi_plan_build(specs, p->grid, p->dev);
+  hipError_t e = multi_plan_build(specs, cuckoo, p->grid, p->dev);
   if (e != hipSuccess) {
     multi_plan_free(p->dev);
     delete p;
@@ -581,13 +571,16 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
 
 int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t s) {
   if (!p) return fail(HT_EINVAL, "plan is NULL");
-  {
+  if (p->dev.nitems) {
     KernelTimer kt("multi_fill", s);
     HT_HIP(multi_plan_launch(p->dev, s));
   }
-  for (const auto& j : p->cuckoo) {
-    int rc = do_find_or_put(j.t, j.keys, j.n, j.out, s);
-    if (rc) return rc;
+  if (p->dev.ncitems) {
+    static const char* const names[3] = {"multi_cuckoo_probe", "multi_cuckoo_evict", "multi_cuckoo_scrub"};
+    for (int ph = 0; ph < 3; ++ph) {
+      KernelTimer kt(names[ph], s);
+      HT_HIP(multi_cuckoo_launch(p->dev, ph, s));
+    }
   }
   return HT_OK;
 }

@@ -533,63 +533,73 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
 
 
 def run_served(b, inputs, torch, dev, nreq=1024, ntables=64, slots_log2=24):
-    """Served request loop: 64 resident bucketed tables of 2^24 slots (2^30
-    slots, 8 GiB), `nreq` requests of log-uniform sizes 2^8..2^20 (70% keys
-    from a synthetic BFS successor stream, 30% random; half find-or-put,
-    half query), pinned host keys and flags (host-device copies included).
-    The sequential per-request baseline is timed first with every request
-    released at 0; its request rate is the saturation rate.  Then Poisson
-    arrivals at 0.5, 0.8 and 1.2 times that rate are served both ways.
-    Latency = completion seen by the host - arrival."""
+    """Served request loop: 64 resident tables of 2^24 slots (2^30 slots,
+    8 GiB), `nreq` requests of log-uniform sizes 2^8..2^20 (70% keys from a
+    synthetic BFS successor stream, 30% random; half find-or-put, half
+    query), pinned host keys and flags (host-device copies included); once
+    with bucketed tables (B = 8, c = 3) and once with Cuckoo tables (c = 3).
+    Per design, the sequential per-request baseline is timed first with every
+    request released at 0; its request rate is the saturation rate.  Then
+    Poisson arrivals at 0.5, 0.8 and 1.2 times that rate are served both
+    ways.  Latency = completion seen by the host - arrival."""
     t0 = time.time()
     stream = inputs.successor_stream(inputs.BfsModel(1), 1 << 23, start_states=(0, 0x123456789ABCDEF))
     base = inputs.served_trace(nreq, ntables, 8, 20, rate=0.0, seed=inputs.SEED_BASE + 5, stream=stream)
     keys = [torch.from_numpy(k.view(np.int64)).pin_memory() for _, _, k, _ in base]
     outs = [torch.empty(k.numel(), dtype=torch.uint8, pin_memory=True) for k in keys]
     total = int(sum(k.numel() for k in keys))
-    tables = [b.Table("bucketed", capacity=1 << slots_log2, nhash=3, bucket_slots=8) for _ in range(ntables)]
     log(f"[bench] served workload: {nreq} requests, {total} keys, {ntables} tables ({time.time() - t0:.1f}s)")
-
-    def run(arrivals, reps=3, **cfg):
-        # best wall time of `reps` runs from cleared tables (runs last tens of ms)
-        best = None
-        for _ in range(reps):
-            for t in tables:
-                t.clear()
-            torch.cuda.synchronize()
-            srv = b.Server(tables, **cfg)
-            reqs = [(op, t, keys[i], arrivals[i]) for i, (op, t, _, _) in enumerate(base)]
-            _, admit, done, groups, st = srv.run(reqs, outs)
-            srv.close()
-            if best is None or st["wall_s"] < best[1]["wall_s"]:
-                best = (done, st)
-        done, st = best
-        lat = (done - np.asarray(arrivals)) * 1e3
-        return {"requests_per_s": round(nreq / st["wall_s"], 1),
-                "mkeys_per_s": round(total / st["wall_s"] / 1e6, 1),
-                "wall_s": round(st["wall_s"], 4),
-                "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
-                "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
-                "groups": st["groups"], "merged_launches": st["merged_launches"],
-                "max_inflight_groups": st["max_inflight_groups"], "throttled": st["throttled"],
-                "peak_staging_MB": round(st["peak_staging"] / 2 ** 20, 1)}
-
-    zeros = [0.0] * nreq
-    seq0 = run(zeros, sequential=True)
-    sat = seq0["requests_per_s"]
     res = {"tables": ntables, "slots_total": ntables << slots_log2, "requests": nreq, "keys": total,
-           "includes_pcie": True, "saturation_requests_per_s": sat,
-           "sequential_backlog": seq0, "served_backlog": run(zeros), "poisson": []}
-    for rho in (0.5, 0.8, 1.2):
-        rate = rho * sat
-        tr = inputs.served_trace(nreq, ntables, 8, 20, rate=rate, seed=inputs.SEED_BASE + 5, stream=stream)
-        arr = [a for _, _, _, a in tr]
-        res["poisson"].append({"rho": rho, "rate_requests_per_s": round(rate, 1),
-                               "sequential": run(arr, sequential=True),
-                               "served": run(arr)})
-        log(f"[bench] served rho={rho}: {res['poisson'][-1]}")
-    for t in tables:
-        t.close()
+           "includes_pcie": True, "designs": {}}
+    for design, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())):
+        tables = [b.Table(design, capacity=1 << slots_log2, nhash=3, **kw) for _ in range(ntables)]
+
+        def run(arrivals, reps=3, **cfg):
+            # best wall time of `reps` runs from cleared tables (runs last tens of ms)
+            best = None
+            for _ in range(reps):
+                for t in tables:
+                    t.clear()
+                torch.cuda.synchronize()
+                srv = b.Server(tables, **cfg)
+                reqs = [(op, t, keys[i], arrivals[i]) for i, (op, t, _, _) in enumerate(base)]
+                _, admit, done, groups, st = srv.run(reqs, outs)
+                srv.close()
+                if best is None or st["wall_s"] < best[1]["wall_s"]:
+                    best = (done, st)
+            done, st = best
+            lat = (done - np.asarray(arrivals)) * 1e3
+            return {"requests_per_s": round(nreq / st["wall_s"], 1),
+                    "mkeys_per_s": round(total / st["wall_s"] / 1e6, 1),
+                    "wall_s": round(st["wall_s"], 4),
+                    "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
+                    "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
+                    "groups": st["groups"], "merged_launches": st["merged_launches"],
+                    "max_inflight_groups": st["max_inflight_groups"], "throttled": st["throttled"],
+                    "peak_staging_MB": round(st["peak_staging"] / 2 ** 20, 1)}
+
+        zeros = [0.0] * nreq
+        seq0 = run(zeros, sequential=True)
+        sat = seq0["requests_per_s"]
+        d = {"saturation_requests_per_s": sat, "sequential_backlog": seq0, "served_backlog": run(zeros),
+             "poisson": []}
+        log(f"[bench] served {design} backlog: sequential {seq0['requests_per_s']} req/s, "
+            f"served {d['served_backlog']['requests_per_s']} req/s")
+        for rho in (0.5, 0.8, 1.2):
+            rate = rho * sat
+            tr = inputs.served_trace(nreq, ntables, 8, 20, rate=rate, seed=inputs.SEED_BASE + 5, stream=stream)
+            arr = [a for _, _, _, a in tr]
+            d["poisson"].append({"rho": rho, "rate_requests_per_s": round(rate, 1),
+                                 "sequential": run(arr, sequential=True),
+                                 "served": run(arr)})
+            p = d["poisson"][-1]
+            log(f"[bench] served {design} rho={rho}: p99 sequential {p['sequential']['latency_ms_p99']} ms, "
+                f"served {p['served']['latency_ms_p99']} ms; req/s {p['sequential']['requests_per_s']} vs "
+                f"{p['served']['requests_per_s']}")
+        res["designs"][design] = d
+        for t in tables:
+            t.close()
+        torch.cuda.synchronize()
     return res
 
 

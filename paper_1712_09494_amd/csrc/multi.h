@@ -35,17 +35,21 @@ struct MultiCuckooSpec {
 
 // Per-stream-slot descriptor buffers for launches whose table set changes
 // every time (pinned host staging + device copy; nothing allocated per launch).
+struct MultiCuckoo;
+
 struct MultiDyn {
   MultiTable* d_tabs = nullptr;
   uint64_t* d_items = nullptr;
   MultiTable* h_tabs = nullptr;
   uint64_t* h_items = nullptr;
+  MultiCuckoo* d_ctabs = nullptr;
+  uint64_t* d_citems = nullptr;
+  MultiCuckoo* h_ctabs = nullptr;
+  uint64_t* h_citems = nullptr;
   void* d_base = nullptr;
   void* h_base = nullptr;
-  uint32_t cap_tabs = 0, cap_items = 0;
+  uint32_t cap_tabs = 0, cap_items = 0;   // per kind
 };
-
-struct MultiCuckoo;
 
 // A prepared many-table launch: descriptors and item lists in one device
 // allocation.
@@ -68,6 +72,9 @@ hipError_t multi_cuckoo_launch(const MultiPlanDev& plan, int phase, hipStream_t 
 hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items);
 void multi_dyn_free(MultiDyn& d);
 uint64_t multi_items_for(uint64_t n);
-hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, uint32_t max_blocks, hipStream_t s);
+// Bucketed tables in one persistent launch, then the three Cuckoo phase
+// launches over the Cuckoo tables; all on stream s.
+hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
+                            uint32_t nc, uint32_t max_blocks, hipStream_t s);
 
 }  // namespace ht

@@ -1,7 +1,7 @@
 // Many bucketed tables in one persistent launch.
 //
 // The find-or-put of every bucketed table is cut into work items of equal
-// size (a power of two between 256 and 4096 keys, chosen so that a launch has
+// size (a power of two between 64 and 4096 keys, chosen so that a launch has
 // about as many items as the device has wave slots); wave w takes items w,
 // w + W, w + 2W, ... of the queue.  The items are equal, so this static
 // split balances, and it needs no shared queue counter (a counter popped by
@@ -123,9 +123,10 @@ __global__ __launch_bounds__(kBlock) void multi_cuckoo_scrub_kernel(const MultiC
 }
 
 // Item size for a launch of `total` keys on a device with `max_waves` wave
-// slots: a power of two in [256, 4096] giving about max_waves items.
+// slots: a power of two in [64, 4096] giving about max_waves items (small
+// launches still fill every wave slot).
 uint64_t multi_chunk(uint64_t total, uint64_t max_waves) {
-  uint64_t c = 256;
+  uint64_t c = 64;
   while (c < 4096 && c * max_waves < total) c <<= 1;
   return c;
 }
@@ -136,6 +137,38 @@ uint32_t multi_grid(uint64_t nitems, uint32_t max_blocks) {
 }
 
 // ---- host side ------------------------------------------------------------
+
+// Fill the descriptors and (table, region) items of `nc` Cuckoo tables.  A
+// region holds at least a whole item's worth of keys (a multiple of 64) and a
+// table never gets more regions than its scratch has per-wave counts.
+// Returns the item count, or ~0 when they would exceed cap_items or a
+// table's counts.
+static uint64_t fill_cuckoo(const MultiCuckooSpec* cs, uint32_t nc, uint64_t max_waves, MultiCuckoo* tabs,
+                            uint64_t* items, uint64_t cap_items) {
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < nc; ++i) total += cs[i].n;
+  const uint64_t chunk = multi_chunk(total, max_waves);
+  uint64_t nitems = 0;
+  for (uint32_t i = 0; i < nc; ++i) {
+    const MultiCuckooSpec& sp = cs[i];
+    MultiCuckoo& m = tabs[i];
+    std::memset(&m, 0, sizeof(m));
+    m.t = sp.t;
+    m.s = sp.s;
+    m.keys = sp.keys;
+    m.out = sp.out;
+    m.n = sp.n;
+    m.paper = sp.paper ? 1u : 0u;
+    const uint64_t maxr = std::max<uint64_t>(sp.max_regions, 1);
+    uint64_t per = std::max<uint64_t>(chunk, (sp.n + maxr - 1) / maxr);
+    per = (per + kWave - 1) / kWave * kWave;
+    m.s.per_wave = per;
+    const uint64_t nr = (sp.n + per - 1) / per;
+    if (nr > maxr || nitems + nr > cap_items) return ~0ull;
+    for (uint64_t r = 0; r < nr; ++r) items[nitems++] = make_item(i, r);
+  }
+  return nitems;
+}
 
 static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
 
@@ -164,31 +197,14 @@ hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, const std::vect
     m.nregions = sp.n ? (uint32_t)((sp.n + m.chunk - 1) / m.chunk) : 0;
     for (uint64_t r = 0; r < m.nregions; ++r) items.push_back(make_item(i, r));
   }
-  // Cuckoo: one region per wave of 64 keys at least; a table never has more
-  // regions than its scratch has per-wave counts
   const uint32_t nc = (uint32_t)cspecs.size();
   std::vector<MultiCuckoo> ctabs(nc);
-  std::vector<uint64_t> citems;
-  uint64_t ctotal = 0;
-  for (const auto& sp : cspecs) ctotal += sp.n;
-  const uint64_t cchunk = multi_chunk(ctotal, max_waves);
-  for (uint32_t i = 0; i < nc; ++i) {
-    const MultiCuckooSpec& sp = cspecs[i];
-    MultiCuckoo& m = ctabs[i];
-    std::memset(&m, 0, sizeof(m));
-    m.t = sp.t;
-    m.s = sp.s;
-    m.keys = sp.keys;
-    m.out = sp.out;
-    m.n = sp.n;
-    m.paper = sp.paper ? 1u : 0u;
-    uint64_t per = std::max<uint64_t>(cchunk, (sp.n + sp.max_regions - 1) / std::max<uint64_t>(sp.max_regions, 1));
-    per = (per + kWave - 1) / kWave * kWave;
-    m.s.per_wave = per;
-    const uint64_t nr = sp.n ? (sp.n + per - 1) / per : 0;
-    if (nr > sp.max_regions) return hipErrorInvalidValue;
-    for (uint64_t r = 0; r < nr; ++r) citems.push_back(make_item(i, r));
-  }
+  uint64_t cap_c = 0;
+  for (const auto& sp : cspecs) cap_c += multi_items_for(sp.n);
+  std::vector<uint64_t> citems(cap_c);
+  const uint64_t ncit = fill_cuckoo(cspecs.data(), nc, max_waves, ctabs.data(), citems.data(), cap_c);
+  if (ncit == ~0ull) return hipErrorInvalidValue;
+  citems.resize(ncit);
   plan.nitems = (uint32_t)items.size();
   plan.ncitems = (uint32_t)citems.size();
   plan.grid = multi_grid(plan.nitems, max_blocks);
@@ -247,18 +263,24 @@ hipError_t multi_cuckoo_launch(const MultiPlanDev& plan, int phase, hipStream_t 
 hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items) {
   d.cap_tabs = cap_tabs;
   d.cap_items = cap_items;
-  const size_t b_tabs = (sizeof(MultiTable) * cap_tabs + 255) / 256 * 256;
-  const size_t b_items = ((size_t)cap_items * 8 + 255) / 256 * 256;
-  hipError_t e = hipMalloc(&d.d_base, b_tabs + b_items);
+  const size_t b_tabs = align256(sizeof(MultiTable) * cap_tabs);
+  const size_t b_items = align256((size_t)cap_items * 8);
+  const size_t b_ctabs = align256(sizeof(MultiCuckoo) * cap_tabs);
+  const size_t bytes = b_tabs + 2 * b_items + b_ctabs;
+  hipError_t e = hipMalloc(&d.d_base, bytes);
   if (e != hipSuccess) return e;
-  e = hipHostMalloc(&d.h_base, b_tabs + b_items, hipHostMallocDefault);
+  e = hipHostMalloc(&d.h_base, bytes, hipHostMallocDefault);
   if (e != hipSuccess) return e;
   char* c = static_cast<char*>(d.d_base);
-  d.d_tabs = reinterpret_cast<MultiTable*>(c);
-  d.d_items = reinterpret_cast<uint64_t*>(c + b_tabs);
   char* h = static_cast<char*>(d.h_base);
+  d.d_tabs = reinterpret_cast<MultiTable*>(c);
   d.h_tabs = reinterpret_cast<MultiTable*>(h);
+  d.d_items = reinterpret_cast<uint64_t*>(c + b_tabs);
   d.h_items = reinterpret_cast<uint64_t*>(h + b_tabs);
+  d.d_ctabs = reinterpret_cast<MultiCuckoo*>(c + b_tabs + b_items);
+  d.h_ctabs = reinterpret_cast<MultiCuckoo*>(h + b_tabs + b_items);
+  d.d_citems = reinterpret_cast<uint64_t*>(c + b_tabs + b_items + b_ctabs);
+  d.h_citems = reinterpret_cast<uint64_t*>(h + b_tabs + b_items + b_ctabs);
   return hipSuccess;
 }
 
@@ -269,13 +291,15 @@ void multi_dyn_free(MultiDyn& d) {
 }
 
 // Number of work items a table of n keys needs.
-uint64_t multi_items_for(uint64_t n) { return (n + 255) / 256; }
+uint64_t multi_items_for(uint64_t n) { return (n + 63) / 64; }
 
-hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, uint32_t max_blocks, hipStream_t s) {
-  if (nt > d.cap_tabs) return hipErrorInvalidValue;
+hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
+                            uint32_t nc, uint32_t max_blocks, hipStream_t s) {
+  if (nt > d.cap_tabs || nc > d.cap_tabs) return hipErrorInvalidValue;
+  const uint64_t max_waves = (uint64_t)max_blocks * (kBlock / kWave);
   uint64_t total = 0;
   for (uint32_t i = 0; i < nt; ++i) total += specs[i].n;
-  const uint64_t chunk = multi_chunk(total, (uint64_t)max_blocks * (kBlock / kWave));
+  const uint64_t chunk = multi_chunk(total, max_waves);
   uint32_t nitems = 0;
   for (uint32_t i = 0; i < nt; ++i) {
     MultiTable& m = d.h_tabs[i];
@@ -289,13 +313,29 @@ hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, ui
     if (nitems + m.nregions > d.cap_items) return hipErrorInvalidValue;
     for (uint64_t r = 0; r < m.nregions; ++r) d.h_items[nitems++] = make_item(i, r);
   }
-  if (nitems == 0) return hipSuccess;
-  hipError_t e = hipMemcpyAsync(d.d_tabs, d.h_tabs, sizeof(MultiTable) * nt, hipMemcpyHostToDevice, s);
-  if (e == hipSuccess) e = hipMemcpyAsync(d.d_items, d.h_items, (size_t)nitems * 8, hipMemcpyHostToDevice, s);
-  if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(multi_fill_kernel, dim3(multi_grid(nitems, max_blocks)), dim3(kBlock), 0, s, d.d_tabs,
-                     d.d_items, nitems);
-  return hipGetLastError();
+  const uint64_t ncit = fill_cuckoo(cspecs, nc, max_waves, d.h_ctabs, d.h_citems, d.cap_items);
+  if (ncit == ~0ull) return hipErrorInvalidValue;
+  hipError_t e = hipSuccess;
+  if (nitems) {
+    e = hipMemcpyAsync(d.d_tabs, d.h_tabs, sizeof(MultiTable) * nt, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.d_items, d.h_items, (size_t)nitems * 8, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(multi_fill_kernel, dim3(multi_grid(nitems, max_blocks)), dim3(kBlock), 0, s, d.d_tabs,
+                       d.d_items, nitems);
+    e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (ncit) {
+    e = hipMemcpyAsync(d.d_ctabs, d.h_ctabs, sizeof(MultiCuckoo) * nc, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(d.d_citems, d.h_citems, (size_t)ncit * 8, hipMemcpyHostToDevice, s);
+    if (e != hipSuccess) return e;
+    const dim3 g(multi_grid(ncit, max_blocks)), b(kBlock);
+    hipLaunchKernelGGL(multi_cuckoo_probe_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
+    hipLaunchKernelGGL(multi_cuckoo_evict_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
+    hipLaunchKernelGGL(multi_cuckoo_scrub_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
+    e = hipGetLastError();
+  }
+  return e;
 }
 
 }  // namespace ht

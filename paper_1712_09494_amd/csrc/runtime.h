@@ -61,6 +61,7 @@ bool is_scripted(const ht_table* t);
 int check_table(const ht_table* t);
 int reserve_scratch(ht_table* t, uint64_t n);
 ht::DevTable launch_view(const ht_table* t);
+ht::CuckooScratch scratch_view(const ht_table* t, uint64_t n);   // per_wave left for the caller
 int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s);
 int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s);
 

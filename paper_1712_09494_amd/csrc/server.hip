@@ -16,10 +16,10 @@
 //     of its table;
 //   - merging: a group takes up to `merge` admissible requests of distinct
 //     tables and up to `group_keys` keys (so small requests are not held
-//     behind large ones); its bucketed find-or-puts run as one many-table
-//     launch, its other requests as their own kernels, all on the group's
-//     stream between the host-to-device copies and the device-to-host
-//     copies;
+//     behind large ones); its find-or-puts run as many-table launches (one
+//     for the bucketed tables, three phase launches for the Cuckoo tables),
+//     its queries as their own kernels, all on the group's stream between
+//     the host-to-device copies and the device-to-host copies;
 //   - overlap: groups on different stream slots run concurrently.
 // The sequential baseline runs one request at a time, waiting for each.
 #include <algorithm>
@@ -234,7 +234,9 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
     return std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
   };
   std::vector<MultiSpec> specs;
+  std::vector<MultiCuckooSpec> cspecs;
   specs.reserve(s->cfg.merge);
+  cspecs.reserve(s->cfg.merge);
   int err = HT_OK;
 
   while (completed < nreq && err == HT_OK) {
@@ -311,6 +313,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
       // issue: keys in, kernels, flags out, completion event
       hipStream_t st = sl.stream;
       specs.clear();
+      cspecs.clear();
       for (size_t k = 0; k < sl.reqs.size() && err == HT_OK; ++k) {
         const ht_request& r = reqs[sl.reqs[k]];
         if (!r.n) continue;
@@ -326,14 +329,25 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
         uint8_t* dflag = reinterpret_cast<uint8_t*>(s->pool.ptr(sl.offs[k]) + (r.n * 8 + 255) / 256 * 256);
         if (r.op == HT_OP_FIND_OR_PUT && tb->cfg.kind == HT_BUCKETED && s->cfg.merge > 1) {
           specs.push_back(MultiSpec{launch_view(tb), dk, dflag, r.n});
+        } else if (r.op == HT_OP_FIND_OR_PUT && s->cfg.merge > 1) {
+          MultiCuckooSpec cs{};
+          cs.t = launch_view(tb);
+          cs.s = scratch_view(tb, r.n);
+          cs.keys = dk;
+          cs.out = dflag;
+          cs.n = r.n;
+          cs.max_regions = (uint64_t)max_blocks(tb) * (kBlock / kWave);
+          cs.paper = (tb->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
+          cspecs.push_back(cs);
         } else if (r.op == HT_OP_FIND_OR_PUT) {
           err = do_find_or_put(tb, dk, r.n, dflag, st);
         } else {
           err = do_query(tb, dk, r.n, dflag, st);
         }
       }
-      if (err == HT_OK && !specs.empty()) {
-        hipError_t e = multi_dyn_launch(sl.dyn, specs.data(), (uint32_t)specs.size(), s->grid, st);
+      if (err == HT_OK && !(specs.empty() && cspecs.empty())) {
+        hipError_t e = multi_dyn_launch(sl.dyn, specs.data(), (uint32_t)specs.size(), cspecs.data(),
+                                        (uint32_t)cspecs.size(), s->grid, st);
         if (e != hipSuccess) err = hip_fail(e, "serving many-table launch");
         ++merged;
       }

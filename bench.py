@@ -56,6 +56,7 @@ def parse():
                     help="only run the served request-loop measurement")
     ap.add_argument("--served-requests", type=int, default=1024)
     ap.add_argument("--no-bfs", action="store_true")
+    ap.add_argument("--no-lds", action="store_true", help="skip the LDS occupancy ablation")
     ap.add_argument("--bfs-only", action="store_true",
                     help="only run the BFS-key (state-space exploration) measurement")
     ap.add_argument("--batched-only", action="store_true",
@@ -153,9 +154,10 @@ def main():
         checks[name] = {"size": sz, "new_flags": nnew, "ok": sz == d and nnew == d}
         assert sz == d and nnew == d, (name, sz, nnew, d)
 
-    # per-design figures and per-kernel durations (HIP events on the launch stream)
+    # per-design figures (HIP events around each batch), then per-kernel
+    # durations in a separate pass (the library's events around every kernel
+    # add gaps between launches, so they stay out of the per-design figures)
     per_design = {}
-    b.ht_timing_enable(True)
     for name in designs:
         t = tables[name]
         t.clear()
@@ -176,6 +178,11 @@ def main():
             "batch_ms_p99": round(float(np.percentile(lat, 99)), 4),
             "ms_total": round(float(lat.sum()), 3),
         }
+    b.ht_timing_enable(True)
+    for name in designs:
+        tables[name].clear()
+        fop_all(tables[name])
+    torch.cuda.synchronize()
     kern = b.ht_timing_report()
     b.ht_timing_enable(False)
     per_kernel = {k: {"launches": c, "avg_ms": round(ms / c, 5), "total_ms": round(ms, 3)}
@@ -189,6 +196,10 @@ def main():
     sweep = None
     if not args.no_sweep:
         sweep = run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out)
+
+    lds = None
+    if not args.no_lds:
+        lds = run_lds_ablation(b, torch, stream, args, d, keys, out)
 
     batched = None
     if not args.no_batched:
@@ -230,6 +241,7 @@ def main():
         "per_kernel": per_kernel,
         "checks": checks,
         "sweep": sweep,
+        "lds_ablation": lds,
         "batched": batched,
         "served": served,
         "bfs": bfs,
@@ -354,6 +366,42 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
                             "ok": hits == int(round(h * args.n))})
             t.close()
             log(f"[bench] sweep {kind} lf={lf} done")
+    return res
+
+
+def run_lds_ablation(b, torch, stream, args, d, keys, out):
+    """The shared-memory setting of Sec. 6 as an occupancy ablation: W2
+    find-or-put (batches of 2^20, LF 0.7) with `lds_bytes` of LDS allocated and
+    unused per 256-thread block.  A compute unit has 160 KiB of LDS and a block
+    puts one wave on each of its 4 SIMDs, so the LDS allows floor(160 KiB /
+    lds_bytes) waves per SIMD (the kernels' registers allow 8)."""
+    res = []
+    cap = int(np.ceil(d / args.lf))
+    for kind in ("bucketed", "cuckoo"):
+        kw = dict(bucket_slots=args.bucket_slots) if kind == "bucketed" else {}
+        for lds in (0, 24 << 10, 32 << 10, 40 << 10, 64 << 10, 80 << 10, 160 << 10):
+            waves = 8 if lds == 0 else min(8, (160 << 10) // lds)
+            try:
+                t = b.Table(kind, capacity=cap, nhash=3, max_batch=args.batch, lds_bytes=lds, **kw)
+            except b.HtError as e:
+                res.append({"design": kind, "lds_bytes": lds, "skipped": str(e)})
+                continue
+            evs = []
+            for s0 in range(0, args.n, args.batch):
+                s1 = min(args.n, s0 + args.batch)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                t.find_or_put(keys[s0:s1], out[s0:s1])
+                e1.record(stream)
+                evs.append((e0, e1))
+            torch.cuda.synchronize()
+            ms = sum(a.elapsed_time(z) for a, z in evs)
+            res.append({"design": kind, "lds_bytes": lds, "waves_per_simd": waves,
+                        "fop_mops": round(args.n / ms / 1e3, 1), "ok": t.size() == d})
+            t.close()
+        log(f"[bench] lds ablation {kind}: " +
+            ", ".join(f"{r['lds_bytes'] >> 10}K:{r.get('fop_mops', '-')}" for r in res if r["design"] == kind))
     return res
 
 

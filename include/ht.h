@@ -108,7 +108,12 @@ typedef struct {
                               0 = grow on demand (the call then allocates) */
   uint32_t bucket_walk;    /* bucketed: consecutive buckets probed after h_c's
                               bucket before the stash; 0 = 64 */
-  uint32_t reserved;
+  uint32_t lds_bytes;      /* ablation of the shared-memory setting of Sec. 6:
+                              bytes of LDS allocated (and left unused) per
+                              256-thread block of the single-table find-or-put
+                              and query kernels, which lowers how many waves a
+                              compute unit holds; 0 = none.  At most the
+                              device's LDS per block (HT_EINVAL otherwise) */
 } ht_config;
 
 typedef struct {

@@ -63,7 +63,7 @@ class HtConfig(C.Structure):
         ("overflow_slots", C.c_uint32),
         ("max_batch", C.c_uint64),
         ("bucket_walk", C.c_uint32),
-        ("reserved", C.c_uint32),
+        ("lds_bytes", C.c_uint32),
     ]
 
 
@@ -492,7 +492,7 @@ class Table:
     def __init__(self, kind: str = "bucketed", capacity: int = 1 << 20, nhash: int = 3,
                  bucket_slots: int = 16, stash_slots: int = 0, max_chain: int = 0, seed: int = 0,
                  flags: int = 0, overflow_slots: int = 0, max_batch: int = 0, keys_per_group: int = 0,
-                 bucket_walk: int = 0):
+                 bucket_walk: int = 0, lds_bytes: int = 0):
         self.kind = kind
         cfg = ht_config_default(KINDS[kind])
         cfg.capacity = int(capacity)
@@ -507,6 +507,7 @@ class Table:
         cfg.keys_per_group = int(keys_per_group)
         if bucket_walk:
             cfg.bucket_walk = int(bucket_walk)
+        cfg.lds_bytes = int(lds_bytes)
         self.nhash = cfg.nhash
         self.handle = ht_create(cfg)
 

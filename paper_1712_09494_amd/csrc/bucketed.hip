@@ -9,11 +9,11 @@ template <int B, int R>
 static hipError_t launch_fop(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
                              bool coherent, bool scripted, hipStream_t s) {
   if (scripted)
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, 1, true, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, 1, true, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
   else if (coherent)
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
   else
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, false>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
   return hipGetLastError();
 }
 
@@ -21,9 +21,9 @@ template <int B, int R>
 static hipError_t launch_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
                                bool scripted, hipStream_t s) {
   if (scripted)
-    hipLaunchKernelGGL((bucketed_query_kernel<B, 1, true>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_query_kernel<B, 1, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
   else
-    hipLaunchKernelGGL((bucketed_query_kernel<B, R, false>), dim3(grid), dim3(kBlock), 0, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_query_kernel<B, R, false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
   return hipGetLastError();
 }
 

@@ -16,9 +16,9 @@ namespace ht {
 hipError_t cuckoo_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
                         uint32_t R, bool scripted, hipStream_t st) {
   if (scripted) {
-    hipLaunchKernelGGL((cuckoo_query_kernel<1, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out);
+    hipLaunchKernelGGL((cuckoo_query_kernel<1, true>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out);
   } else {
-#define HT_Q(RR) hipLaunchKernelGGL((cuckoo_query_kernel<RR, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out)
+#define HT_Q(RR) hipLaunchKernelGGL((cuckoo_query_kernel<RR, false>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out)
     HT_R_DISPATCH(HT_Q)
 #undef HT_Q
   }
@@ -30,17 +30,17 @@ hipError_t cuckoo_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uin
                         const CuckooScratch& s, uint32_t grid, uint32_t R, bool scripted, bool paper_order,
                         hipStream_t st) {
   if (scripted && paper_order) {
-    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s);
+    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, true>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s);
   } else if (scripted) {
-    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s);
+    hipLaunchKernelGGL((cuckoo_probe_kernel<1, true, false>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s);
   } else if (paper_order) {
 #define HT_P(RR) \
-  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, true>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s)
+  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, true>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
     HT_R_DISPATCH(HT_P)
 #undef HT_P
   } else {
 #define HT_P(RR) \
-  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, false>), dim3(grid), dim3(kBlock), 0, st, t, keys, n, out, s)
+  hipLaunchKernelGGL((cuckoo_probe_kernel<RR, false, false>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
     HT_R_DISPATCH(HT_P)
 #undef HT_P
   }
@@ -51,9 +51,9 @@ hipError_t cuckoo_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uin
 hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const CuckooScratch& s, uint32_t grid,
                         bool scripted, hipStream_t st) {
   if (scripted)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(grid), dim3(kBlock), t.lds, st, t, n, out, s);
   else
-    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(grid), dim3(kBlock), 0, st, t, n, out, s);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(grid), dim3(kBlock), t.lds, st, t, n, out, s);
   return hipGetLastError();
 }
 

@@ -79,7 +79,7 @@ struct DevTable {
   uint32_t flags;
   uint32_t kind;
   uint32_t walk;            // bucketed: extra consecutive buckets after h_c
-  uint32_t pad_;
+  uint32_t lds;             // host side: dynamic LDS bytes per block at launch (ablation)
 };
 
 // Scratch of the Cuckoo find-or-put (owned by the table).

@@ -252,6 +252,12 @@ int validate_config(const ht_config* c) {
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL))
     return fail(HT_EINVAL, "unknown flag bits");
+  if (c->lds_bytes) {
+    int dev = 0, lim = 0;
+    (void)hipGetDevice(&dev);
+    if (hipDeviceGetAttribute(&lim, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) != hipSuccess) lim = 65536;
+    if (c->lds_bytes > (uint32_t)lim) return fail(HT_EINVAL, "lds_bytes above the device's LDS per block");
+  }
   return HT_OK;
 }
 
@@ -286,6 +292,7 @@ void setup_geometry(ht_table* t) {
   t->dev.kind = c.kind;
   if (!c.bucket_walk) c.bucket_walk = 64;
   t->dev.walk = (c.kind == HT_BUCKETED && !(c.flags & HT_FLAG_BUCKETED_PAPER_FULL)) ? c.bucket_walk : 0;
+  t->dev.lds = c.lds_bytes;
 }
 
 int check_table(const ht_table* t) {

@@ -68,6 +68,7 @@ def test_bad_configs_rejected_without_gpu():
     c = b.ht_config_default(b.HT_CUCKOO); c.capacity = 64; c.stash_slots = 100; bad.append(c)
     c = b.ht_config_default(b.HT_CUCKOO); c.capacity = 64; c.flags = 1 << 9; bad.append(c)
     c = b.ht_config_default(7); c.capacity = 64; bad.append(c)
+    c = b.ht_config_default(b.HT_BUCKETED); c.capacity = 64; c.lds_bytes = 1 << 30; bad.append(c)
     for c in bad:
         assert lib.ht_create(C.byref(c), C.byref(h)) == b.HT_EINVAL
         assert h.value is None

@@ -1,4 +1,6 @@
 """CPU oracle (test infrastructure only; see set_oracle)."""
-from .set_oracle import LoopOracle, Oracle, first_occurrence_flags
+from .set_oracle import (LoopOracle, Oracle, VecLoopOracle, VecOracle, first_occurrence_flags,
+                         first_occurrence_flags_vec)
 
-__all__ = ["LoopOracle", "Oracle", "first_occurrence_flags"]
+__all__ = ["LoopOracle", "Oracle", "VecLoopOracle", "VecOracle", "first_occurrence_flags",
+           "first_occurrence_flags_vec"]

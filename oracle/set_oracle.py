@@ -1,4 +1,4 @@
-"""CPU oracle for batched find-or-put and query of 64-bit keys.
+"""CPU oracle for batched find-or-put and query of 64-bit keys and state vectors.
 
 TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the
 CPU-baseline leg of the benchmark import this module; the library path never
@@ -17,6 +17,11 @@ plain definition of a set over 64-bit words, applied in index order:
 
 Every 64-bit value is a legal key (including the all-ones word that a table
 may reserve internally as its empty marker).
+
+State vectors of several words (GPUexplore stores a state as a vector of
+words, Sec. 3.2 and 4.2) are keys in the same sense: two vectors are the same
+key exactly when all their words are equal.  ``VecLoopOracle`` and
+``VecOracle`` apply the same definition to keys given as rows of W words.
 
 Two forms are given:
 
@@ -113,6 +118,80 @@ class Oracle:
         return self.keys.copy()
 
 
+def _rows(keys, w: int) -> np.ndarray:
+    a = np.asarray(keys)
+    if a.dtype == np.int64:
+        a = a.view(np.uint64)
+    return np.ascontiguousarray(a, dtype=np.uint64).reshape(-1, w)
+
+
+def _void(rows: np.ndarray) -> np.ndarray:
+    """One opaque item per row: equal items exactly when all words are equal."""
+    w = rows.shape[1]
+    return np.ascontiguousarray(rows).view(np.dtype((np.void, 8 * w))).reshape(-1)
+
+
+class VecLoopOracle:
+    """The set definition over vectors of w words: a Python set of tuples."""
+
+    def __init__(self, w: int):
+        self.w = w
+        self.s: set[tuple] = set()
+
+    def find_or_put(self, keys) -> list[int]:
+        out = []
+        for row in _rows(keys, self.w).tolist():
+            k = tuple(row)
+            if k in self.s:
+                out.append(0)
+            else:
+                self.s.add(k)
+                out.append(1)
+        return out
+
+    def query(self, keys) -> list[int]:
+        return [1 if tuple(row) in self.s else 0 for row in _rows(keys, self.w).tolist()]
+
+    @property
+    def size(self) -> int:
+        return len(self.s)
+
+
+class VecOracle:
+    """The set definition over vectors of w words, with numpy: each row is
+    one key; first occurrences within a call from ``np.unique`` over whole
+    rows, membership by binary search of the sorted member rows."""
+
+    def __init__(self, w: int, initial=None):
+        self.w = w
+        self.keys = _void(np.zeros((0, w), dtype=U64))
+        if initial is not None:
+            self.keys = np.unique(_void(_rows(initial, w)))
+
+    def find_or_put(self, keys) -> np.ndarray:
+        v = _void(_rows(keys, self.w))
+        out = np.zeros(v.size, dtype=np.uint8)
+        if v.size == 0:
+            return out
+        uniq, first = np.unique(v, return_index=True)
+        absent = ~_member(self.keys, uniq)
+        out[first[absent]] = 1
+        if absent.any():
+            self.keys = np.unique(np.concatenate([self.keys, uniq[absent]]))
+        return out
+
+    def query(self, keys) -> np.ndarray:
+        return _member(self.keys, _void(_rows(keys, self.w))).astype(np.uint8)
+
+    @property
+    def size(self) -> int:
+        return int(self.keys.size)
+
+    def dump(self) -> np.ndarray:
+        """Member vectors as an (n, w) array, rows in byte order."""
+        return self.keys.view(U64).reshape(-1, self.w).copy()
+
+
 def first_occurrence_flags(keys) -> np.ndarray:
     """find_or_put of the whole sequence into an empty set (uint8 flags).
 
@@ -124,5 +203,15 @@ def first_occurrence_flags(keys) -> np.ndarray:
     out = np.zeros(k.size, dtype=np.uint8)
     if k.size:
         _, first = np.unique(k, return_index=True)
+        out[first] = 1
+    return out
+
+
+def first_occurrence_flags_vec(keys, w: int) -> np.ndarray:
+    """first_occurrence_flags for keys given as rows of w words."""
+    v = _void(_rows(keys, w))
+    out = np.zeros(v.size, dtype=np.uint8)
+    if v.size:
+        _, first = np.unique(v, return_index=True)
         out[first] = 1
     return out

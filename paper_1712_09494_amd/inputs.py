@@ -177,6 +177,50 @@ def random_sequence(n: int, distinct: int, seed: int) -> np.ndarray:
     return key_of_index(idx[perm], seed)
 
 
+def vector_of_index(idx: np.ndarray, w: int, seed: int, structured: bool = False) -> np.ndarray:
+    """(len(idx), w) state vectors, one per index, distinct for distinct indices.
+
+    Random form: word j of vector i is fmix64(i ^ s_j) with per-word seeds.
+    Structured form (like packed process states): the index's bits are spread
+    over the words a few at a time and every word keeps many zero bits, so
+    vectors share most of their words with many others.  Word 0 of the
+    structured form carries the low 12 bits, word 1 the next 12, ..., and the
+    last word the rest.
+    """
+    idx = np.asarray(idx, dtype=np.uint64)
+    out = np.empty((idx.size, w), dtype=np.uint64)
+    if structured:
+        rest = idx.copy()
+        for j in range(w):
+            if j < w - 1:
+                part = rest & np.uint64(0xFFF)
+                rest = rest >> np.uint64(12)
+            else:
+                part = rest
+            # 4 bits per process slot, 3 of them used: like local states packed in a word
+            spread = np.zeros_like(part)
+            for b in range(0, 12 if j < w - 1 else 48, 3):
+                spread |= ((part >> np.uint64(b)) & np.uint64(7)) << np.uint64(4 * (b // 3))
+            out[:, j] = spread ^ np.uint64((seed * 0x9E3779B97F4A7C15 + j) & 0xF0F0F0F0F0F0F0F0)
+        return out
+    for j in range(w):
+        out[:, j] = fmix64(idx ^ _u(seed + 0x9E3779B97F4A7C15 * (j + 1)))
+    return out
+
+
+def vector_sequence(n: int, distinct: int, w: int, seed: int, structured: bool = False) -> np.ndarray:
+    """(n, w) sequence of state vectors with exactly ``distinct`` distinct rows
+    (same index recipe as random_sequence)."""
+    assert 0 < distinct <= n
+    idx = np.empty(n, dtype=np.uint64)
+    idx[:distinct] = np.arange(distinct, dtype=np.uint64)
+    if n > distinct:
+        r = splitmix64_stream(seed ^ 0xD1B54A32D192ED03, n - distinct)
+        idx[distinct:] = uniform_below(r, distinct)
+    perm = feistel_permutation(n, seed)
+    return vector_of_index(idx[perm], w, seed, structured)
+
+
 def query_sequence(n: int, distinct: int, hit_rate: float, seed: int,
                    query_seed: int | None = None) -> np.ndarray:
     """n queries against the key set {key_of_index(i) : i < distinct}.

@@ -120,3 +120,17 @@ def test_served_trace_shape():
     assert all(np.array_equal(x[2], y[2]) and x[:2] == y[:2] for x, y in zip(reqs, again))
     ops = [op for op, *_ in reqs]
     assert 60 < ops.count("query") < 140
+
+
+@pytest.mark.parametrize("structured", [False, True])
+@pytest.mark.parametrize("w", [2, 4])
+def test_vector_generators(w, structured):
+    v = inputs.vector_of_index(np.arange(50000), w, seed=4, structured=structured)
+    assert v.shape == (50000, w) and v.dtype == np.uint64
+    assert np.unique(v, axis=0).shape[0] == 50000
+    seq = inputs.vector_sequence(30000, 25000, w, seed=6, structured=structured)
+    assert seq.shape == (30000, w)
+    assert np.unique(seq, axis=0).shape[0] == 25000
+    if structured:
+        # most vectors share their later words with many others
+        assert np.unique(v[:, -1]).size < 50000 // 10

@@ -14,7 +14,8 @@ import os
 import numpy as np
 import pytest
 
-from oracle import LoopOracle, Oracle, first_occurrence_flags
+from oracle import (LoopOracle, Oracle, VecLoopOracle, VecOracle, first_occurrence_flags,
+                    first_occurrence_flags_vec)
 from paper_1712_09494_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -186,6 +187,89 @@ def test_pins_catch_planted_mistakes(bad):
         got = o.find_or_put(np.array(seq[:cut], dtype=np.uint64)).tolist() + \
             o.find_or_put(np.array(seq[cut:], dtype=np.uint64)).tolist()
         if got != scan_new(seq):
+            caught = True
+            break
+    assert caught
+
+
+# ---- state vectors of several words --------------------------------------
+
+M = (1 << 64) - 1
+VEC_ALPHABET = [(0, 0), (0, 1), (1, 0), (M, M)]   # pairs sharing one word, and all-ones
+
+
+def vec_sequences(max_len):
+    for n in range(max_len + 1):
+        for t in itertools.product(VEC_ALPHABET, repeat=n):
+            yield list(t)
+
+
+def test_vec_bruteforce_against_scan():
+    """Every sequence of length <= 6 over four 2-word vectors, split into two
+    calls, against the quadratic scan over whole tuples."""
+    count = 0
+    for seq in vec_sequences(6):
+        exp = scan_new(seq)
+        arr = np.array(seq, dtype=np.uint64).reshape(-1, 2)
+        cut = len(seq) // 2
+        o = VecOracle(2)
+        got = o.find_or_put(arr[:cut]).tolist() + o.find_or_put(arr[cut:]).tolist()
+        assert got == exp, seq
+        lo = VecLoopOracle(2)
+        assert lo.find_or_put(arr) == exp, seq
+        assert o.size == lo.size == len(set(seq))
+        q = o.query(np.array(VEC_ALPHABET, dtype=np.uint64)).tolist()
+        assert q == [1 if a in seq else 0 for a in VEC_ALPHABET]
+        assert sorted(map(tuple, o.dump().tolist())) == sorted(set(seq))
+        count += 1
+    assert count == sum(4 ** n for n in range(7))
+
+
+def test_vec_reduces_to_single_words():
+    """One-word vectors, and vectors whose words all equal one value x, behave
+    exactly like the 64-bit keys x."""
+    rng = np.random.default_rng(5)
+    for _ in range(5):
+        x = rng.integers(0, 300, size=2000).astype(np.uint64)
+        x[::37] = np.uint64(M)
+        o1, o4, ov = Oracle(), VecOracle(4), VecOracle(1)
+        for part in np.array_split(x, 4):
+            exp = o1.find_or_put(part)
+            assert np.array_equal(ov.find_or_put(part), exp)
+            assert np.array_equal(o4.find_or_put(np.repeat(part, 4).reshape(-1, 4)), exp)
+        q = rng.integers(0, 400, size=500).astype(np.uint64)
+        assert np.array_equal(o4.query(np.repeat(q, 4).reshape(-1, 4)), o1.query(q))
+
+
+def test_vec_invariants_random():
+    """Stored set = distinct rows (counted with np.unique over axis 0); one new
+    per distinct absent row; rows differing in any one word are different keys."""
+    rng = np.random.default_rng(9)
+    for w in (2, 4):
+        base = rng.integers(0, 1 << 62, size=(3000, w), dtype=np.int64).astype(np.uint64)
+        seq = base[rng.integers(0, 3000, size=9000)]
+        o = VecOracle(w)
+        f = np.concatenate([o.find_or_put(part) for part in np.array_split(seq, 5)])
+        assert int(f.sum()) == o.size == np.unique(seq, axis=0).shape[0]
+        assert np.array_equal(f, first_occurrence_flags_vec(seq, w))
+        for j in range(w):                   # change one word: a different key
+            alt = seq[:100].copy()
+            alt[:, j] ^= np.uint64(1 << 63)
+            assert o.query(alt).sum() == 0
+        assert o.query(seq).all()
+
+
+def test_vec_pins_catch_word0_only():
+    """A planted mistake -- comparing only the first word -- fails the pins."""
+    class Word0(VecOracle):
+        def find_or_put(self, keys):
+            k = np.asarray(keys, dtype=np.uint64).reshape(-1, self.w).copy()
+            k[:, 1:] = 0
+            return super().find_or_put(k)
+    caught = False
+    for seq in vec_sequences(3):
+        arr = np.array(seq, dtype=np.uint64).reshape(-1, 2)
+        if Word0(2).find_or_put(arr).tolist() != scan_new(seq):
             caught = True
             break
     assert caught

@@ -57,6 +57,8 @@ def parse():
     ap.add_argument("--served-requests", type=int, default=1024)
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-lds", action="store_true", help="skip the LDS occupancy ablation")
+    ap.add_argument("--no-vectors", action="store_true", help="skip the state-vector tables")
+    ap.add_argument("--vectors-only", action="store_true", help="only run the state-vector tables")
     ap.add_argument("--bfs-only", action="store_true",
                     help="only run the BFS-key (state-space exploration) measurement")
     ap.add_argument("--batched-only", action="store_true",
@@ -90,6 +92,9 @@ def main():
         return
     if args.served_only:
         print(json.dumps({"served": run_served(b, inputs, torch, dev, args.served_requests)}), flush=True)
+        return
+    if args.vectors_only:
+        print(json.dumps({"vectors": run_vectors(b, inputs, torch, dev, stream)}), flush=True)
         return
     if args.batched_only:
         print(json.dumps({"batched": run_batched(b, inputs, torch, dev, stream)}), flush=True)
@@ -201,6 +206,10 @@ def main():
     if not args.no_lds:
         lds = run_lds_ablation(b, torch, stream, args, d, keys, out)
 
+    vectors = None
+    if not args.no_vectors:
+        vectors = run_vectors(b, inputs, torch, dev, stream)
+
     batched = None
     if not args.no_batched:
         batched = run_batched(b, inputs, torch, dev, stream)
@@ -242,6 +251,7 @@ def main():
         "checks": checks,
         "sweep": sweep,
         "lds_ablation": lds,
+        "vectors": vectors,
         "batched": batched,
         "served": served,
         "bfs": bfs,
@@ -402,6 +412,86 @@ def run_lds_ablation(b, torch, stream, args, d, keys, out):
             t.close()
         log(f"[bench] lds ablation {kind}: " +
             ", ".join(f"{r['lds_bytes'] >> 10}K:{r.get('fop_mops', '-')}" for r in res if r["design"] == kind))
+    return res
+
+
+def run_vectors(b, inputs, torch, dev, stream, n=1 << 24, batch=1 << 20, lf=0.7):
+    """State vectors of 2 and 4 words: n vectors (10% duplicates, random and
+    structured generators) find-or-put in batches at load factor `lf` into each
+    design, then n queries at hit rate 0.5.  Per design and width: vectors/s,
+    batch p50/p99, per-kernel averages and the bytes model's fraction of HBM."""
+    res = []
+    d = int(0.9 * n)
+    for structured in (False, True):
+        for w in (2, 4):
+            t0 = time.time()
+            seq = inputs.vector_sequence(n, d, w, seed=inputs.SEED_BASE + 7 + w, structured=structured)
+            keys = torch.from_numpy(seq.view(np.int64).reshape(-1)).to(dev)
+            del seq
+            q_idx = np.concatenate([np.arange(0, d, 2 * d // n + 1)[: n // 2],
+                                    np.arange(d, d + n - n // 2)]).astype(np.uint64)
+            qv = inputs.vector_of_index(q_idx, w, seed=inputs.SEED_BASE + 7 + w, structured=structured)
+            qk = torch.from_numpy(qv.view(np.int64).reshape(-1)).to(dev)
+            nq_hit = min(n // 2, len(range(0, d, 2 * d // n + 1)))
+            del qv
+            out = torch.empty(n, dtype=torch.uint8, device=dev)
+            qout = torch.empty(qk.numel() // w, dtype=torch.uint8, device=dev)
+            log(f"[bench] vectors w={w} structured={structured}: workload ready ({time.time() - t0:.1f}s)")
+            for kind in ("bucketed", "cuckoo"):
+                kw = dict(bucket_slots=8) if kind == "bucketed" else {}
+                t = b.Table(kind, capacity=int(np.ceil(d / lf)), nhash=3, key_words=w, max_batch=batch, **kw)
+
+                def fill(evs=None):
+                    t.clear()
+                    for s0 in range(0, n, batch):
+                        s1 = min(n, s0 + batch)
+                        if evs is not None:
+                            e0 = torch.cuda.Event(enable_timing=True)
+                            e1 = torch.cuda.Event(enable_timing=True)
+                            e0.record(stream)
+                        t.find_or_put(keys[s0 * w:s1 * w], out[s0:s1])
+                        if evs is not None:
+                            e1.record(stream)
+                            evs.append((e0, e1))
+                fill()
+                evs = []
+                fill(evs)
+                torch.cuda.synchronize()
+                lat = np.array([a.elapsed_time(z) for a, z in evs])
+                ok = t.size() == d and t.sync_status() == b.HT_OK
+                b.ht_timing_enable(True)
+                fill()
+                torch.cuda.synchronize()
+                kern = b.ht_timing_report()
+                b.ht_timing_enable(False)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                t.query(qk, qout)
+                e1.record(stream)
+                torch.cuda.synchronize()
+                qms = e0.elapsed_time(e1)
+                hits = int(qout.sum(dtype=torch.int64).item())
+                nb = (n + batch - 1) // batch
+                per_kernel = {k: round(ms / c, 5) for k, (c, ms) in kern.items() if k != "clear"}
+                # least bytes per batch: key words + flag + one slot line per vector; a new
+                # vector adds a dirtied half-line and its arena row, a found one reads its row
+                kb = n / nb * (w * 8 + 1 + LINE) + d / nb * (HALF + w * 8) + (n - d) / nb * LINE
+                res.append({"design": kind, "key_words": w, "structured": structured, "vectors": n,
+                            "distinct": d, "batch": batch, "load_factor": lf,
+                            "fop_mvectors_per_s": round(n / lat.sum() / 1e3, 1),
+                            "batch_ms_p50": round(float(np.percentile(lat, 50)), 4),
+                            "batch_ms_p99": round(float(np.percentile(lat, 99)), 4),
+                            "kernel_avg_ms": per_kernel,
+                            "hbm_frac_least_bytes": round(kb / (lat.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4),
+                            "query_mvectors_per_s": round(qout.numel() / qms / 1e3, 1),
+                            "ok": bool(ok and hits == nq_hit)})
+                log(f"[bench] vectors {kind} w={w} structured={structured}: "
+                    f"{res[-1]['fop_mvectors_per_s']} M/s fop, {res[-1]['query_mvectors_per_s']} M/s query, "
+                    f"ok={res[-1]['ok']}")
+                t.close()
+            del keys, qk, out, qout
+            torch.cuda.empty_cache()
     return res
 
 

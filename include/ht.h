@@ -114,6 +114,14 @@ typedef struct {
                               and query kernels, which lowers how many waves a
                               compute unit holds; 0 = none.  At most the
                               device's LDS per block (HT_EINVAL otherwise) */
+  uint32_t key_words;      /* words per key: 1 (64-bit keys), 2 or 4 (state
+                              vectors of 128 or 256 bits, the multi-word state
+                              vectors of GPUexplore, Sec. 3.2 and 4.2); 0 = 1.
+                              A vector table stores each member once in an
+                              arena of (capacity + stash_slots + overflow_slots)
+                              entries and keeps 64-bit handles in its slots;
+                              see ht_find_or_put for the key layout */
+  uint32_t reserved;       /* must be 0 */
 } ht_config;
 
 typedef struct {
@@ -145,9 +153,11 @@ int ht_create_simple(uint32_t kind, uint64_t capacity, uint32_t nhash, ht_table*
 int ht_destroy(ht_table* t);
 
 /* Find-or-put (Sec. 5; Sec. 4.1 insertion for cuckoo, Sec. 4.2 for bucketed).
- * d_keys: n keys (uint64, device); d_out_is_new: n bytes (device), may be
- * NULL when the flags are not wanted.  Grows the table's scratch (allocating,
- * synchronising) when n exceeds what was reserved. */
+ * d_keys: n keys (uint64, device); for a table with key_words W > 1, n
+ * vectors of W words each, row-major (n * W words, 16-byte aligned; HT_EINVAL
+ * otherwise).  d_out_is_new: n bytes (device), may be NULL when the flags are
+ * not wanted.  Grows the table's scratch (allocating, synchronising) when n
+ * exceeds what was reserved. */
 int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n,
                    uint8_t* d_out_is_new, hipStream_t stream);
 
@@ -211,8 +221,9 @@ int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t stream);
 int ht_size(ht_table* t, uint64_t* out_n, hipStream_t stream);
 
 /* Write every member once (any order) to d_out (device, room for `cap`
- * keys); *out_n = member count (even when it exceeds cap, in which case only
- * cap keys are written).  Synchronises. */
+ * keys; a vector table writes rows of key_words words); *out_n = member
+ * count (even when it exceeds cap, in which case only cap keys are written).
+ * Synchronises. */
 int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n,
             hipStream_t stream);
 
@@ -228,7 +239,8 @@ int ht_clear(ht_table* t, hipStream_t stream);
 int ht_stats(ht_table* t, ht_stats_t* out, hipStream_t stream);
 
 /* Host-side hash of the table: the bucket index (bucketed) or slot index
- * (cuckoo) that h_j (0-based j < nhash) assigns to `key`. */
+ * (cuckoo) that h_j (0-based j < nhash) assigns to `key`.  For a vector table
+ * `key` is a handle's hash bits (the handle shifted right by 34). */
 int ht_hash_index(const ht_table* t, uint64_t key, uint32_t j, uint64_t* out_index);
 
 /* Test mode (HT_FLAG_SCRIPTED_HASH): install `nkeys` scripted keys with

@@ -64,6 +64,8 @@ class HtConfig(C.Structure):
         ("max_batch", C.c_uint64),
         ("bucket_walk", C.c_uint32),
         ("lds_bytes", C.c_uint32),
+        ("key_words", C.c_uint32),
+        ("reserved", C.c_uint32),
     ]
 
 
@@ -322,10 +324,19 @@ def ht_destroy(h: int) -> None:
     _check(load().ht_destroy(h), "ht_destroy")
 
 
-def ht_find_or_put(h: int, keys, out=None, stream=None):
+def _count(k, w: int) -> int:
+    if k.numel() % w:
+        raise ValueError(f"key tensor of {k.numel()} words is not a whole number of {w}-word keys")
+    return k.numel() // w
+
+
+def ht_find_or_put(h: int, keys, out=None, stream=None, key_words: int = 1):
+    """keys: n 64-bit keys, or for a vector table n rows of key_words words
+    (any shape with n * key_words elements, row-major)."""
     k = _key_tensor(keys)
-    o = _out_tensor(out, k.numel(), k)
-    _check(load().ht_find_or_put(h, k.data_ptr(), k.numel(), o.data_ptr(), _stream_handle(stream)),
+    n = _count(k, key_words)
+    o = _out_tensor(out, n, k)
+    _check(load().ht_find_or_put(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(stream)),
            "ht_find_or_put")
     return o
 
@@ -333,10 +344,11 @@ def ht_find_or_put(h: int, keys, out=None, stream=None):
 ht_insert = ht_find_or_put
 
 
-def ht_query(h: int, keys, out=None, stream=None):
+def ht_query(h: int, keys, out=None, stream=None, key_words: int = 1):
     k = _key_tensor(keys)
-    o = _out_tensor(out, k.numel(), k)
-    _check(load().ht_query(h, k.data_ptr(), k.numel(), o.data_ptr(), _stream_handle(stream)), "ht_query")
+    n = _count(k, key_words)
+    o = _out_tensor(out, n, k)
+    _check(load().ht_query(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(stream)), "ht_query")
     return o
 
 
@@ -413,14 +425,16 @@ def ht_stats(h: int, stream=None) -> dict:
     return s.as_dict()
 
 
-def ht_dump(h: int, stream=None):
-    """Members as an int64 GPU tensor (uint64 bits), any order."""
+def ht_dump(h: int, stream=None, key_words: int = 1):
+    """Members as an int64 GPU tensor (uint64 bits), any order; for a vector
+    table an (n, key_words) tensor."""
     torch = _torch()
     n = ht_size(h, stream)
-    buf = torch.empty(max(n, 1), dtype=torch.int64, device="cuda")
+    buf = torch.empty((max(n, 1), key_words), dtype=torch.int64, device="cuda")
     got = _u64()
-    _check(load().ht_dump(h, buf.data_ptr(), buf.numel(), C.byref(got), _stream_handle(stream)), "ht_dump")
-    return buf[: got.value]
+    _check(load().ht_dump(h, buf.data_ptr(), buf.shape[0], C.byref(got), _stream_handle(stream)), "ht_dump")
+    buf = buf[: got.value]
+    return buf.reshape(-1) if key_words == 1 else buf
 
 
 def ht_dump_raw(h: int, stream=None):
@@ -492,7 +506,7 @@ class Table:
     def __init__(self, kind: str = "bucketed", capacity: int = 1 << 20, nhash: int = 3,
                  bucket_slots: int = 16, stash_slots: int = 0, max_chain: int = 0, seed: int = 0,
                  flags: int = 0, overflow_slots: int = 0, max_batch: int = 0, keys_per_group: int = 0,
-                 bucket_walk: int = 0, lds_bytes: int = 0):
+                 bucket_walk: int = 0, lds_bytes: int = 0, key_words: int = 1):
         self.kind = kind
         cfg = ht_config_default(KINDS[kind])
         cfg.capacity = int(capacity)
@@ -508,6 +522,8 @@ class Table:
         if bucket_walk:
             cfg.bucket_walk = int(bucket_walk)
         cfg.lds_bytes = int(lds_bytes)
+        cfg.key_words = int(key_words)
+        self.key_words = int(key_words)
         self.nhash = cfg.nhash
         self.handle = ht_create(cfg)
 
@@ -529,12 +545,12 @@ class Table:
         self.close()
 
     def find_or_put(self, keys, out=None, stream=None):
-        return ht_find_or_put(self.handle, keys, out, stream)
+        return ht_find_or_put(self.handle, keys, out, stream, self.key_words)
 
     insert = find_or_put
 
     def query(self, keys, out=None, stream=None):
-        return ht_query(self.handle, keys, out, stream)
+        return ht_query(self.handle, keys, out, stream, self.key_words)
 
     def size(self, stream=None) -> int:
         return ht_size(self.handle, stream)
@@ -543,7 +559,7 @@ class Table:
         return ht_stats(self.handle, stream)
 
     def dump(self, stream=None):
-        return ht_dump(self.handle, stream)
+        return ht_dump(self.handle, stream, self.key_words)
 
     def dump_raw(self, stream=None):
         return ht_dump_raw(self.handle, stream)

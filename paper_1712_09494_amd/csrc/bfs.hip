@@ -104,6 +104,7 @@ extern "C" int ht_bfs_explore(ht_table* t, const ht_bfs_model* model, uint64_t i
   int rc = check_table(t);
   if (rc) return rc;
   if (!model) return fail(HT_EINVAL, "model is NULL");
+  if (t->cfg.key_words > 1) return fail(HT_EINVAL, "the exploration packs states into single-word keys");
   BfsModelDev m;
   static_assert(sizeof(BfsModelDev) == sizeof(ht_bfs_model), "model layout");
   std::memcpy(&m, model, sizeof(m));

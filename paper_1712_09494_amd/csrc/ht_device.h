@@ -21,6 +21,7 @@ constexpr int kBlock = 256;          // 4 waves per workgroup
 constexpr int kSpread = 16;          // hot counters are spread over 16 lines
 constexpr int kLineWords = 16;       // 128-byte line = 16 words
 constexpr int kMaxHash = 8;
+constexpr int kArenaBits = 34;       // vector tables: arena index bits of a handle
 
 // Hash family: h_j(k) = floor(mix64(k ^ s_j) * range / 2^64).
 // mix64 is the splitmix64 finalizer (Steele, Lea & Flood 2014), a bijection
@@ -52,6 +53,9 @@ struct Counters {
   unsigned int overflow_count;  // appends to the overflow list (may exceed its length)
   unsigned int lost;            // appends that found the overflow list full
   unsigned int pad[28];
+  // vector tables: entries taken in each of the kSpread arena ranges (may
+  // exceed the range size; the excess was never handed out)
+  unsigned long long arena_next[kSpread * kLineWords];
 };
 
 // Scripted hash row (test mode): key and its c hash values.
@@ -80,6 +84,11 @@ struct DevTable {
   uint32_t kind;
   uint32_t walk;            // bucketed: extra consecutive buckets after h_c
   uint32_t lds;             // host side: dynamic LDS bytes per block at launch (ablation)
+  uint64_t* arena;          // vector tables: member vectors, key_words words each
+  uint64_t arena_cap;       // arena entries per range (kSpread ranges)
+  uint64_t vseed;           // vector tables: seed of the vector hash
+  uint32_t key_words;       // words per key (1: single-word keys)
+  uint32_t pad_;
 };
 
 // Scratch of the Cuckoo find-or-put (owned by the table).

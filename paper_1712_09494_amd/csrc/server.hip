@@ -132,6 +132,7 @@ int ht_server_create(ht_table* const* tables, uint32_t ntables, const ht_server_
     int rc = check_table(tables[i]);
     if (rc) return rc;
     if (is_scripted(tables[i])) return fail(HT_EINVAL, "scripted-hash tables cannot be served");
+    if (tables[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables cannot be served");
   }
   ht_server_config c;
   ht_server_config_default(&c);

@@ -25,6 +25,13 @@ hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, co
                         uint32_t, bool, bool, hipStream_t);
 hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, hipStream_t);
 hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, hipStream_t);
+hipError_t vec_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
+                     hipStream_t);
+hipError_t vec_insert(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
+                      uint32_t, hipStream_t);
+hipError_t vec_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, hipStream_t);
+hipError_t vec_dump(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t, unsigned long long*, uint32_t,
+                    uint32_t, hipStream_t);
 hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
@@ -148,6 +155,7 @@ void draw_constants(ht_table* t) {
   for (uint32_t j = 0; j < kMaxHash; ++j) t->dev.seed[j] = t->rng.next();
   t->dev.stash_seed = t->rng.next();
   t->dset_seed = t->rng.next();
+  t->dev.vseed = t->rng.next();
 }
 
 int free_storage(ht_table* t) {
@@ -165,7 +173,12 @@ int alloc_storage(ht_table* t) {
   const size_t ovf_bytes = align_up((size_t)t->dev.overflow_slots * 8, 256);
   const size_t ctr_bytes = align_up(sizeof(Counters), 256);
   const size_t misc_bytes = 256;
-  const size_t total = slot_bytes + stash_bytes + ovf_bytes + ctr_bytes + misc_bytes;
+  const uint32_t W = t->cfg.key_words;
+  // vector arena: kSpread ranges that together hold every possible member
+  const uint64_t members = t->nslots + t->dev.stash_slots + t->dev.overflow_slots;
+  t->dev.arena_cap = W > 1 ? (members + kSpread - 1) / kSpread : 0;
+  const size_t arena_bytes = align_up(t->dev.arena_cap * kSpread * W * 8, 256);
+  const size_t total = slot_bytes + stash_bytes + ovf_bytes + ctr_bytes + misc_bytes + arena_bytes;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, total);
   if (e != hipSuccess) {
@@ -179,6 +192,9 @@ int alloc_storage(ht_table* t) {
   t->dev.overflow = reinterpret_cast<uint64_t*>(c + slot_bytes + stash_bytes);
   t->dev.ctr = reinterpret_cast<Counters*>(c + slot_bytes + stash_bytes + ovf_bytes);
   t->misc = reinterpret_cast<unsigned long long*>(c + slot_bytes + stash_bytes + ovf_bytes + ctr_bytes);
+  t->dev.arena = W > 1 ? reinterpret_cast<uint64_t*>(c + slot_bytes + stash_bytes + ovf_bytes + ctr_bytes +
+                                                     misc_bytes)
+                       : nullptr;
   return HT_OK;
 }
 
@@ -205,7 +221,7 @@ int free_scratch(ht_table* t) {
 
 // Cuckoo scratch for batches up to n keys (one allocation).
 int reserve_scratch(ht_table* t, uint64_t n) {
-  if (t->cfg.kind != HT_CUCKOO) return HT_OK;
+  if (t->cfg.kind != HT_CUCKOO && t->cfg.key_words <= 1) return HT_OK;
   if (n <= t->scratch_n && t->dset) return HT_OK;
   if (n < 1024) n = 1024;
   HT_HIP(hipDeviceSynchronize());
@@ -252,6 +268,14 @@ int validate_config(const ht_config* c) {
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL))
     return fail(HT_EINVAL, "unknown flag bits");
+  if (c->key_words != 0 && c->key_words != 1 && c->key_words != 2 && c->key_words != 4)
+    return fail(HT_EINVAL, "key_words must be 0, 1, 2 or 4");
+  if (c->reserved) return fail(HT_EINVAL, "reserved must be 0");
+  if (c->key_words > 1) {
+    if (c->flags & HT_FLAG_SCRIPTED_HASH) return fail(HT_EINVAL, "scripted hashes need single-word keys");
+    if (c->capacity + 65536ull + (c->overflow_slots ? c->overflow_slots : 65536u) + 64 >= (1ull << kArenaBits) - 1)
+      return fail(HT_EINVAL, "vector table capacity above 2^34 entries");
+  }
   if (c->lds_bytes) {
     int dev = 0, lim = 0;
     (void)hipGetDevice(&dev);
@@ -293,6 +317,8 @@ void setup_geometry(ht_table* t) {
   if (!c.bucket_walk) c.bucket_walk = 64;
   t->dev.walk = (c.kind == HT_BUCKETED && !(c.flags & HT_FLAG_BUCKETED_PAPER_FULL)) ? c.bucket_walk : 0;
   t->dev.lds = c.lds_bytes;
+  if (!c.key_words) c.key_words = 1;
+  t->dev.key_words = c.key_words;
 }
 
 int check_table(const ht_table* t) {
@@ -346,7 +372,38 @@ CuckooScratch scratch_view(const ht_table* t, uint64_t n) {
   return sc;
 }
 
+// Launch shape of the one-lane-per-key kernels: blocks and keys per wave.
+static void lane_grid(const ht_table* t, uint64_t n, uint32_t keys_per_lane, uint64_t& blocks, uint64_t& per_wave) {
+  const uint64_t waves_needed = (n + (uint64_t)kWave * keys_per_lane - 1) / ((uint64_t)kWave * keys_per_lane);
+  blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
+  const uint64_t nwaves = blocks * 4;
+  per_wave = (n + nwaves - 1) / nwaves;
+}
+
+static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
+  int rc = reserve_scratch(t, n);
+  if (rc != HT_OK) return rc;
+  const DevTable d = launch_view(t);
+  uint64_t blocks = 0;
+  CuckooScratch sc = scratch_view(t, n);
+  lane_grid(t, n, 1, blocks, sc.per_wave);
+  {
+    KernelTimer kt("vec_probe", s);
+    HT_HIP(vec_probe(d, keys, n, out, sc, (uint32_t)blocks, t->cfg.key_words, s));
+  }
+  {
+    KernelTimer kt("vec_insert", s);
+    HT_HIP(vec_insert(d, keys, n, out, sc, (uint32_t)blocks, t->cfg.key_words, s));
+  }
+  {
+    KernelTimer kt("vec_scrub", s);
+    HT_HIP(cuckoo_scrub(n, sc, (uint32_t)blocks, s));
+  }
+  return HT_OK;
+}
+
 int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
+  if (t->cfg.key_words > 1) return vec_find_or_put(t, keys, n, out, s);
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
@@ -384,6 +441,12 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
 
 int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
   const DevTable d = launch_view(t);
+  if (t->cfg.key_words > 1) {
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    KernelTimer kt("vec_query", s);
+    HT_HIP(vec_query(d, keys, n, out, (uint32_t)blocks, t->cfg.key_words, s));
+    return HT_OK;
+  }
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
   if (t->cfg.kind == HT_BUCKETED) {
@@ -411,7 +474,7 @@ int dump_members(ht_table* t, uint64_t** d_buf, uint64_t* count, hipStream_t s) 
   if (rc) return rc;
   const uint64_t upper = spread_sum(h.size) + ovf.size() + 1;
   uint64_t* buf = nullptr;
-  hipError_t e = hipMalloc(&buf, std::max<uint64_t>(upper, 1) * 8);
+  hipError_t e = hipMalloc(&buf, std::max<uint64_t>(upper, 1) * 8 * t->cfg.key_words);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(HT_ENOMEM, "hipMalloc of dump buffer failed");
@@ -505,6 +568,8 @@ int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_o
   if (n == 0) return HT_OK;
   if (!d_keys) return fail(HT_EINVAL, "keys is NULL");
   if (n >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
+  if (t->cfg.key_words > 1 && (reinterpret_cast<uintptr_t>(d_keys) & 15))
+    return fail(HT_EINVAL, "vector keys must be 16-byte aligned");
   return do_find_or_put(t, d_keys, n, d_out_is_new, s);
 }
 
@@ -517,6 +582,8 @@ int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_out_fou
   if (rc) return rc;
   if (n == 0) return HT_OK;
   if (!d_keys || !d_out_found) return fail(HT_EINVAL, "keys or out is NULL");
+  if (t->cfg.key_words > 1 && (reinterpret_cast<uintptr_t>(d_keys) & 15))
+    return fail(HT_EINVAL, "vector keys must be 16-byte aligned");
   return do_query(t, d_keys, n, d_out_found, s);
 }
 
@@ -538,6 +605,7 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
     if (n[i] && !d_keys[i]) return fail(HT_EINVAL, "keys is NULL");
     if (n[i] >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
     if (is_scripted(t[i])) return fail(HT_EINVAL, "scripted-hash tables are not supported by the multi-table call");
+    if (t[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables are not supported by the multi-table call");
     if (t[i]->cfg.kind == HT_CUCKOO) {
       rc = reserve_scratch(t[i], n[i]);     // so that launches allocate nothing
       if (rc) return rc;
@@ -636,7 +704,7 @@ int ht_size(ht_table* t, uint64_t* out_n, hipStream_t s) {
   rc = read_counters(t, &h, s);
   if (rc) return rc;
   uint64_t n = spread_sum(h.size);
-  if (t->cfg.kind == HT_BUCKETED && h.overflow_count) {
+  if (t->cfg.kind == HT_BUCKETED && t->cfg.key_words == 1 && h.overflow_count) {
     std::vector<uint64_t> ovf;
     rc = overflow_keys(t, h, ovf, s);
     if (rc) return rc;
@@ -653,6 +721,22 @@ int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n, hipStre
   if (!d_out && cap) return fail(HT_EINVAL, "d_out is NULL");
   HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->misc), 2, s));
   const uint32_t g = max_blocks(t);
+  if (t->cfg.key_words > 1) {
+    // members are the arena entries named by the handles in slots, stash and overflow list
+    Counters h;
+    rc = read_counters(t, &h, s);
+    if (rc) return rc;
+    const uint32_t W = t->cfg.key_words;
+    const uint64_t novf = std::min<uint64_t>(h.overflow_count, t->dev.overflow_slots);
+    HT_HIP(vec_dump(t->dev.slots, t->nslots, t->dev.arena, d_out, cap, t->misc, g, W, s));
+    HT_HIP(vec_dump(t->dev.stash, t->dev.stash_slots, t->dev.arena, d_out, cap, t->misc, g, W, s));
+    HT_HIP(vec_dump(t->dev.overflow, novf, t->dev.arena, d_out, cap, t->misc, g, W, s));
+    unsigned long long nv = 0;
+    HT_HIP(hipMemcpyAsync(&nv, t->misc, 8, hipMemcpyDeviceToHost, s));
+    HT_HIP(hipStreamSynchronize(s));
+    *out_n = nv;
+    return HT_OK;
+  }
   HT_HIP(compact_words(t->dev.slots, t->nslots, d_out, cap, t->misc, g, s));
   HT_HIP(compact_words(t->dev.stash, t->dev.stash_slots, d_out, cap, t->misc, g, s));
   Counters h;

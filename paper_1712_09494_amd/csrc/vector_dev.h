@@ -1,0 +1,366 @@
+// Keys that are state vectors of W 64-bit words (W = 2 or 4).  GPUexplore
+// keeps each state as a vector of words in its bucketed table (Sec. 3.2,
+// Sec. 4.2); the Cuckoo table of Sec. 4.1 moves keys with single-word
+// exchanges, which a multi-word key cannot use directly.
+//
+// Layout.  Every member vector is written once into the table's arena (W
+// words per entry, append-only).  Table slots, stash and overflow list hold
+// 64-bit handles: the top 30 bits of the vector's hash H and a 34-bit arena
+// index.  Bucket and slot positions are functions of those 30 hash bits, so
+// a handle carries everything an eviction chain needs and a chain never reads
+// the arena.  A handle is never all ones (arena indices stay below 2^34 - 1),
+// so the empty marker needs no special key.
+//
+// Find-or-put in three kernels, like the single-word Cuckoo table:
+//   1. lookup (read-only): compare hash bits, then the arena words; vectors
+//      found report 0, the others are listed with their hash;
+//   2. insert: the listed vectors are deduplicated in the scratch set by
+//      batch index (equal vectors compared word by word in the batch); each
+//      winner reports 1, takes an arena entry (one counter atomic per wave),
+//      writes its words and places its handle: bucketed -- lowest empty slot
+//      along the bucket sequence; Cuckoo -- first empty candidate slot, else
+//      the exchange chain of Sec. 4.1 from h_1; then stash, overflow list.
+//      Winners are distinct and absent, so placing needs no comparison and
+//      nothing in this kernel reads a vector another lane is writing;
+//   3. scrub the scratch set (the single-word Cuckoo scrub kernel).
+// Lookups stop early by the same rules as the single-word tables: a bucket
+// with an empty slot ends the bucket sequence (slots fill as a prefix and are
+// never emptied), and a Cuckoo lookup stops at an empty candidate when the
+// handle's c slot indices are distinct.
+#pragma once
+#include "cuckoo_dev.h"
+
+namespace ht {
+
+constexpr uint64_t kArenaMask = (1ull << kArenaBits) - 1;
+
+// Hash of a vector: the words folded through mix64 in order, seeded per table.
+template <int W>
+__device__ __forceinline__ uint64_t vec_hash(const uint64_t (&v)[W], uint64_t seed) {
+  uint64_t h = mix64(v[0] ^ seed);
+#pragma unroll
+  for (int j = 1; j < W; ++j) h = mix64(h ^ mix64(v[j] + 0x9e3779b97f4a7c15ull * (uint64_t)j));
+  return h;
+}
+
+__device__ __forceinline__ uint64_t handle_hb(uint64_t hd) { return hd >> kArenaBits; }
+__device__ __forceinline__ uint64_t handle_idx(uint64_t hd) { return hd & kArenaMask; }
+
+// W words from a 16-byte aligned address.
+template <int W>
+__device__ __forceinline__ void load_vec(const uint64_t* p, uint64_t (&v)[W]) {
+#pragma unroll
+  for (int j = 0; j < W; j += 2) {
+    const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(p + j);
+    v[j] = x.x;
+    v[j + 1] = x.y;
+  }
+}
+
+template <int W>
+__device__ __forceinline__ bool vec_eq(const uint64_t (&a)[W], const uint64_t (&b)[W]) {
+  bool e = true;
+#pragma unroll
+  for (int j = 0; j < W; ++j) e &= a[j] == b[j];
+  return e;
+}
+
+// Handle hd holds vector v: hash bits first, then the arena words.
+template <int W>
+__device__ __forceinline__ bool vec_holds(const DevTable& t, uint64_t hd, uint64_t hb, const uint64_t (&v)[W]) {
+  if (hd == kEmpty || handle_hb(hd) != hb) return false;
+  uint64_t a[W];
+  load_vec<W>(t.arena + handle_idx(hd) * W, a);
+  return vec_eq<W>(a, v);
+}
+
+// q-th bucket of the bucket sequence: h_1..h_c, then the walk of consecutive
+// buckets after h_c (wrapping at the end of the table), given the (q-1)-th.
+__device__ __forceinline__ uint64_t vec_bucket(const DevTable& t, uint64_t hb, uint32_t q, uint64_t prev) {
+  if (q < t.nhash) return hidx<false>(t, hb, q);
+  return prev + 1 == t.nrange ? 0 : prev + 1;
+}
+
+template <int W>
+__device__ bool vec_lookup_bucketed(const DevTable& t, uint64_t hb, const uint64_t (&v)[W]) {
+  const uint32_t B = t.bucket_slots;
+  const uint32_t steps = t.nhash + t.walk;
+  uint64_t b = 0;
+  for (uint32_t q = 0; q < steps; ++q) {
+    b = vec_bucket(t, hb, q, b);
+    const uint64_t* bk = t.slots + b * B;
+    for (uint32_t s = 0; s < B; s += 2) {
+      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(bk + s);
+      if (x.x == kEmpty) return false;          // prefix: the rest of the sequence is unused
+      if (vec_holds<W>(t, x.x, hb, v)) return true;
+      if (x.y == kEmpty) return false;
+      if (vec_holds<W>(t, x.y, hb, v)) return true;
+    }
+  }
+  return false;
+}
+
+template <int W>
+__device__ bool vec_lookup_cuckoo(const DevTable& t, uint64_t hb, const uint64_t (&v)[W]) {
+  const bool dist = hashes_distinct<false>(t, hb);
+  for (uint32_t j = 0; j < t.nhash; ++j) {
+    const uint64_t hd = t.slots[hidx<false>(t, hb, j)];
+    if (hd == kEmpty) {
+      if (dist) return false;
+      continue;
+    }
+    if (vec_holds<W>(t, hd, hb, v)) return true;
+  }
+  return false;
+}
+
+// Stash (positions from the hash bits, linear probing) and overflow list.
+template <int W>
+__device__ bool vec_stash_query(const DevTable& t, uint64_t hb, const uint64_t (&v)[W], uint32_t sc,
+                                uint32_t oc) {
+  if (sc) {
+    const uint32_t S = t.stash_slots;
+    uint32_t p = stash_start(t, hb);
+    for (uint32_t i = 0; i < S; ++i) {
+      const uint64_t hd = t.stash[p];
+      if (hd == kEmpty) break;
+      if (vec_holds<W>(t, hd, hb, v)) return true;
+      p = (p + 1) & (S - 1);
+    }
+  }
+  if (oc) {
+    const uint32_t m = oc < t.overflow_slots ? oc : t.overflow_slots;
+    for (uint32_t i = 0; i < m; ++i)
+      if (vec_holds<W>(t, t.overflow[i], hb, v)) return true;
+  }
+  return false;
+}
+
+template <int W>
+__device__ __forceinline__ bool vec_find(const DevTable& t, uint64_t hb, const uint64_t (&v)[W], uint32_t sc,
+                                         uint32_t oc) {
+  const bool f = t.kind == HT_KIND_BUCKETED ? vec_lookup_bucketed<W>(t, hb, v) : vec_lookup_cuckoo<W>(t, hb, v);
+  return f || ((sc | oc) && vec_stash_query<W>(t, hb, v, sc, oc));
+}
+
+// Place a handle of a vector known to be absent (no comparison needed).
+__device__ inline void vec_stash_put(const DevTable& t, uint64_t hd) {
+  const uint32_t S = t.stash_slots;
+  uint32_t p = stash_start(t, handle_hb(hd));
+  for (uint32_t i = 0; i < S; ++i) {
+    if (cas64(&t.stash[p], kEmpty, hd) == kEmpty) {
+      add_agent(&t.ctr->stash_count, 1u);
+      return;
+    }
+    p = (p + 1) & (S - 1);
+  }
+  const uint32_t pos = add_agent(&t.ctr->overflow_count, 1u);
+  if (pos < t.overflow_slots)
+    store_coherent(&t.overflow[pos], hd);
+  else
+    add_agent(&t.ctr->lost, 1u);
+}
+
+__device__ inline void vec_place_bucketed(const DevTable& t, uint64_t hd) {
+  const uint64_t hb = handle_hb(hd);
+  const uint32_t B = t.bucket_slots;
+  const uint32_t steps = t.nhash + t.walk;
+  uint64_t b = 0;
+  for (uint32_t q = 0; q < steps; ++q) {
+    b = vec_bucket(t, hb, q, b);
+    uint64_t* bk = t.slots + b * B;
+    // lowest empty slot first; a lost race moves on to the next slot
+    for (uint32_t s = 0; s < B; ++s)
+      if (bk[s] == kEmpty && cas64(&bk[s], kEmpty, hd) == kEmpty) return;
+  }
+  vec_stash_put(t, hd);
+}
+
+__device__ inline void vec_place_cuckoo(const DevTable& t, uint64_t hd, unsigned long long& nevict) {
+  const uint32_t c = t.nhash;
+  for (uint32_t j = 0; j < c; ++j) {
+    uint64_t* p = &t.slots[hidx<false>(t, handle_hb(hd), j)];
+    if (*p == kEmpty && cas64(p, kEmpty, hd) == kEmpty) return;
+  }
+  // every candidate taken: the exchange chain of Sec. 4.1 from h_1
+  uint64_t x = hd;
+  uint64_t slot = hidx<false>(t, handle_hb(x), 0);
+  for (uint32_t step = 0;; ++step) {
+    const uint64_t old = exch64(&t.slots[slot], x);
+    if (old == kEmpty) return;
+    x = old;
+    ++nevict;
+    if (step + 1 >= t.max_chain) break;
+    // next hash after the last one that maps x here, skipping ones that also do
+    uint64_t h[kMaxHash];
+    int a = -1;
+    for (uint32_t j = 0; j < c; ++j) {
+      h[j] = hidx<false>(t, handle_hb(x), j);
+      if (h[j] == slot) a = (int)j;
+    }
+    uint32_t nj = (uint32_t)(a + 1) % c;
+    for (uint32_t tries = 0; h[nj] == slot && tries < c; ++tries) nj = (nj + 1) % c;
+    if (h[nj] == slot) break;
+    slot = h[nj];
+  }
+  vec_stash_put(t, x);
+}
+
+// Kernel 1: lookup; misses listed per wave region as (hash, batch index).
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_probe_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                            uint64_t n, uint8_t* __restrict__ out,
+                                                            CuckooScratch s) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  const uint64_t begin = wave * s.per_wave;
+  uint64_t end = begin + s.per_wave;
+  if (end > n) end = n;
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  uint32_t nlist = 0;
+  for (uint64_t base = begin; base < end; base += kWave) {
+    const uint64_t i = base + lane;
+    bool miss = false;
+    uint64_t H = 0;
+    if (i < end) {
+      uint64_t v[W];
+      load_vec<W>(keys + i * W, v);
+      H = vec_hash<W>(v, t.vseed);
+      if (vec_find<W>(t, H >> kArenaBits, v, sc, oc)) {
+        if (out) out[i] = 0;
+      } else {
+        miss = true;
+      }
+    }
+    const uint64_t mm = ballot(miss);
+    if (miss) {
+      const uint64_t slot = begin + nlist + lanes_below(mm);
+      s.wkey[slot] = H;
+      s.wmeta[slot] = i;
+    }
+    nlist += (uint32_t)__popcll(mm);
+  }
+  if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
+}
+
+// Kernel 2: deduplicate the listed vectors, store the winners and place their
+// handles.  Each pass of the wave takes up to 64 listed vectors.
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                             uint64_t n, uint8_t* __restrict__ out,
+                                                             CuckooScratch s) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = lane_id();
+  const uint64_t begin = wave * s.per_wave;
+  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
+  unsigned long long nnew = 0, nevict = 0;
+  for (uint32_t e0 = 0; e0 < cnt; e0 += kWave) {
+    const uint32_t e = e0 + (uint32_t)lane;
+    bool winner = false;
+    uint64_t H = 0;
+    uint64_t v[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) v[j] = 0;
+    if (e < cnt) {
+      H = s.wkey[begin + e];
+      const uint64_t i = s.wmeta[begin + e];
+      load_vec<W>(keys + i * W, v);
+      uint64_t p = mix64(H ^ s.dset_seed) & s.dset_mask;
+      for (;;) {
+        const uint64_t old = cas64(&s.dset[p], kEmpty, i);
+        if (old == kEmpty) {
+          winner = true;
+          break;
+        }
+        if (old < n) {                     // the set holds indices of this batch only
+          uint64_t u[W];
+          load_vec<W>(keys + old * W, u);
+          if (vec_eq<W>(u, v)) break;      // an equal vector of the batch won
+        }
+        p = (p + 1) & s.dset_mask;
+      }
+      if (out) out[i] = winner ? 1 : 0;
+      s.wmeta[begin + e] = winner ? p : ~0ull;   // scratch-set slot for the scrub kernel
+    }
+    if (!ballot(winner)) continue;
+    // arena entries: one counter atomic per wave and range; a wave starts at
+    // its own range and moves on while a range is full
+    uint64_t idx = ~0ull;
+    bool want = winner;
+    for (uint32_t a = 0; a < (uint32_t)kSpread; ++a) {
+      const uint64_t wm = ballot(want);
+      if (!wm) break;
+      const uint32_t rg = (uint32_t)((wave + a) % kSpread);
+      unsigned long long first = 0;
+      if (lane == 0) first = add_agent(&t.ctr->arena_next[rg * kLineWords], (unsigned long long)__popcll(wm));
+      first = shfl64(first, 0);
+      const uint64_t avail = first < t.arena_cap ? t.arena_cap - first : 0;
+      const uint64_t rank = lanes_below(wm);
+      if (want && rank < avail) {
+        idx = (uint64_t)rg * t.arena_cap + first + rank;
+        want = false;
+      }
+    }
+    if (winner) {
+      ++nnew;
+      if (idx == ~0ull) {
+        add_agent(&t.ctr->lost, 1u);     // only after more members than slots + stash + overflow
+      } else {
+#pragma unroll
+        for (int j = 0; j < W; j += 2)
+          *reinterpret_cast<ulonglong2*>(t.arena + idx * W + j) = make_ulonglong2(v[j], v[j + 1]);
+        const uint64_t hd = ((H >> kArenaBits) << kArenaBits) | idx;
+        if (t.kind == HT_KIND_BUCKETED)
+          vec_place_bucketed(t, hd);
+        else
+          vec_place_cuckoo(t, hd, nevict);
+      }
+    }
+  }
+  wave_count(t.ctr->size, nnew, (uint32_t)wave);
+  wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
+}
+
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_query_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                            uint64_t n, uint8_t* __restrict__ out) {
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) {
+    uint64_t v[W];
+    load_vec<W>(keys + i * W, v);
+    const uint64_t H = vec_hash<W>(v, t.vseed);
+    out[i] = vec_find<W>(t, H >> kArenaBits, v, sc, oc) ? 1 : 0;
+  }
+}
+
+// Members: the arena entries named by the handles in `handles[0, nh)`.
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_dump_kernel(const uint64_t* __restrict__ handles, uint64_t nh,
+                                                           const uint64_t* __restrict__ arena,
+                                                           uint64_t* __restrict__ dst, uint64_t cap,
+                                                           unsigned long long* count) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const int lane = lane_id();
+  for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); base < nh; base += stride) {
+    const uint64_t i = base + lane;
+    const uint64_t hd = i < nh ? handles[i] : kEmpty;
+    const bool keep = hd != kEmpty;
+    const uint64_t m = ballot(keep);
+    if (!m) continue;
+    unsigned long long b = 0;
+    if (lane == 0) b = add_agent(count, (unsigned long long)__popcll(m));
+    b = shfl64(b, 0);
+    if (keep) {
+      const uint64_t pos = b + lanes_below(m);
+      if (pos < cap) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) dst[pos * W + j] = arena[handle_idx(hd) * W + j];
+      }
+    }
+  }
+}
+
+}  // namespace ht

@@ -58,6 +58,8 @@ def parse():
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-lds", action="store_true", help="skip the LDS occupancy ablation")
     ap.add_argument("--no-vectors", action="store_true", help="skip the state-vector tables")
+    ap.add_argument("--no-single-pass", action="store_true", help="skip the single-pass Cuckoo ablation")
+    ap.add_argument("--single-pass-only", action="store_true", help="only run the single-pass Cuckoo ablation")
     ap.add_argument("--vectors-only", action="store_true", help="only run the state-vector tables")
     ap.add_argument("--bfs-only", action="store_true",
                     help="only run the BFS-key (state-space exploration) measurement")
@@ -92,6 +94,9 @@ def main():
         return
     if args.served_only:
         print(json.dumps({"served": run_served(b, inputs, torch, dev, args.served_requests)}), flush=True)
+        return
+    if args.single_pass_only:
+        print(json.dumps({"single_pass": run_single_pass(b, inputs, torch, dev, stream)}), flush=True)
         return
     if args.vectors_only:
         print(json.dumps({"vectors": run_vectors(b, inputs, torch, dev, stream)}), flush=True)
@@ -206,6 +211,10 @@ def main():
     if not args.no_lds:
         lds = run_lds_ablation(b, torch, stream, args, d, keys, out)
 
+    single = None
+    if not args.no_single_pass:
+        single = run_single_pass(b, inputs, torch, dev, stream)
+
     vectors = None
     if not args.no_vectors:
         vectors = run_vectors(b, inputs, torch, dev, stream)
@@ -252,6 +261,7 @@ def main():
         "sweep": sweep,
         "lds_ablation": lds,
         "vectors": vectors,
+        "single_pass_ablation": single,
         "batched": batched,
         "served": served,
         "bfs": bfs,
@@ -492,6 +502,51 @@ def run_vectors(b, inputs, torch, dev, stream, n=1 << 24, batch=1 << 20, lf=0.7)
                 t.close()
             del keys, qk, out, qout
             torch.cuda.empty_cache()
+    return res
+
+
+def run_single_pass(b, inputs, torch, dev, stream, n=1 << 24, batch=1 << 20):
+    """Ablation: the paper's single-pass Cuckoo insertion against the
+    three-kernel one, on n keys in batches, for 10% duplicates at load factor
+    0.5 / 0.7 / 0.9 and for BFS-like duplication (6.7 occurrences per key) at
+    0.7.  Reports both rates and the single pass's duplicate stores (entries
+    in slots and stash minus distinct keys) and extra "new" reports."""
+    res = []
+    for dup_per_key, lf in ((1 / 0.9, 0.5), (1 / 0.9, 0.7), (1 / 0.9, 0.9), (6.7, 0.7)):
+        d = int(n / dup_per_key)
+        seq = inputs.random_sequence(n, d, seed=inputs.SEED_BASE + 9)
+        keys = torch.from_numpy(seq.view(np.int64)).to(dev)
+        del seq
+        out = torch.empty(n, dtype=torch.uint8, device=dev)
+        c = 4 if lf > 0.85 else 3
+        row = {"keys": n, "distinct": d, "occurrences_per_key": round(n / d, 2), "load_factor": lf, "nhash": c}
+        for name, flags in (("three_kernel", 0), ("single_pass", b.HT_FLAG_CUCKOO_SINGLE_PASS)):
+            t = b.Table("cuckoo", capacity=int(np.ceil(d / lf)), nhash=c, flags=flags, max_batch=batch)
+            ms = 0.0
+            for rep in range(2):                       # warm-up fill, then the timed one
+                t.clear()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for s0 in range(0, n, batch):
+                    t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+            r = b.u64(t.dump_raw())
+            r = r[r != b.EMPTY]
+            uniq = np.unique(r).size
+            row[name] = {"mops": round(n / ms / 1e3, 1), "duplicate_stores": int(r.size - uniq),
+                         "reported_new": t.size(), "found_all": bool(b.u64(t.query(keys)).all()),
+                         "overflow": t.stats()["overflow_count"]}
+            t.close()
+        res.append(row)
+        log(f"[bench] single pass occ={row['occurrences_per_key']} lf={lf}: three kernels "
+            f"{row['three_kernel']['mops']} Mops/s, single pass {row['single_pass']['mops']} Mops/s, "
+            f"duplicate stores {row['single_pass']['duplicate_stores']}, extra new reports "
+            f"{row['single_pass']['reported_new'] - d}")
+        del keys, out
+        torch.cuda.empty_cache()
     return res
 
 

@@ -86,7 +86,14 @@ enum {
    * stash, as the table of Sec. 4.2 declares itself full at that point.
    * Without the flag the probe first walks up to bucket_walk consecutive
    * buckets after h_c's bucket (same sequence for every inserter of a key). */
-  HT_FLAG_BUCKETED_PAPER_FULL = 1u << 3
+  HT_FLAG_BUCKETED_PAPER_FULL = 1u << 3,
+  /* Cuckoo, ablation only: one kernel per find-or-put doing the lookup and
+   * the eviction chain of Sec. 4.1 in the same pass, with the check of
+   * Sec. 5.1.1 (a thread that evicts its own key stops).  Keys repeated in a
+   * batch can then be stored twice and reported new more than once (a lookup
+   * misses a copy that another thread holds in flight); exact only for
+   * batches without repeated keys.  Not combinable with key_words > 1. */
+  HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4
 };
 
 typedef struct {

@@ -33,6 +33,7 @@ HT_FLAG_CUCKOO_PAPER_ORDER = 1 << 0
 HT_FLAG_CACHED_LOADS = 1 << 1
 HT_FLAG_SCRIPTED_HASH = 1 << 2
 HT_FLAG_BUCKETED_PAPER_FULL = 1 << 3
+HT_FLAG_CUCKOO_SINGLE_PASS = 1 << 4
 
 EMPTY = (1 << 64) - 1
 

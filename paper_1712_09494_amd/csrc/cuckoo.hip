@@ -47,6 +47,16 @@ hipError_t cuckoo_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uin
   return hipGetLastError();
 }
 
+// The paper's single-pass insertion (ablation; see cuckoo_dev.h).
+hipError_t cuckoo_single_pass(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
+                              bool scripted, hipStream_t st) {
+  if (scripted)
+    hipLaunchKernelGGL((cuckoo_single_pass_kernel<true>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out);
+  else
+    hipLaunchKernelGGL((cuckoo_single_pass_kernel<false>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out);
+  return hipGetLastError();
+}
+
 // Kernel 2: deduplicate the listed keys and run their eviction chains.
 hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const CuckooScratch& s, uint32_t grid,
                         bool scripted, hipStream_t st) {

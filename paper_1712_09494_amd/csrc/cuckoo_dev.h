@@ -345,6 +345,70 @@ __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
 }
 
+// Single pass (HT_FLAG_CUCKOO_SINGLE_PASS), the insertion as Sec. 4.1 and
+// Sec. 5.1.1 give it, kept to measure what the three kernels above prevent:
+// one lane per key looks the key up in its c slots (and the stash), and on a
+// miss exchanges it into h_1 and follows the eviction chain; a lane that
+// evicts a copy of the key it is carrying stops there.  A lookup that runs
+// while another lane holds a copy of its key in flight misses it, so a key
+// can end up stored twice (a duplicate store) and reported new more than
+// once.  Exact for batches without repeated keys.
+template <bool SCRIPTED>
+__global__ __launch_bounds__(kBlock) void cuckoo_single_pass_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                                     uint64_t n, uint8_t* __restrict__ out) {
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  const uint32_t c = t.nhash;
+  unsigned long long nnew = 0, nevict = 0;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  for (uint64_t base = first - (first & (kWave - 1)); base < n; base += stride) {
+    const uint64_t i = base + lane_id();
+    if (i >= n) continue;
+    const uint64_t k = keys[i];
+    uint32_t res = 0;
+    if (k == kEmpty) {
+      res = sentinel_put(t);
+    } else {
+      bool hit = false;
+      for (uint32_t j = 0; j < c && !hit; ++j) hit = t.slots[hidx<SCRIPTED>(t, k, j)] == k;
+      if (!hit && (sc | oc)) hit = stash_query(t, k, sc, oc);
+      if (!hit) {
+        res = 1;
+        uint64_t x = k;
+        uint64_t slot = hidx<SCRIPTED>(t, k, 0);
+        for (uint32_t step = 0;; ++step) {
+          const uint64_t old = exch64(&t.slots[slot], x);
+          if (old == kEmpty) break;
+          if (old == x) {                  // evicted a copy of the key it carries: stop
+            if (x == k) res = 0;
+            break;
+          }
+          x = old;
+          ++nevict;
+          uint64_t h[kMaxHash];
+          int a = -1;
+          for (uint32_t j = 0; j < c; ++j) {
+            h[j] = hidx<SCRIPTED>(t, x, j);
+            if (h[j] == slot) a = (int)j;
+          }
+          uint32_t nj = (uint32_t)(a + 1) % c;
+          for (uint32_t tries = 0; h[nj] == slot && tries < c; ++tries) nj = (nj + 1) % c;
+          if (step + 1 >= t.max_chain || h[nj] == slot) {
+            stash_put(t, x);
+            break;
+          }
+          slot = h[nj];
+        }
+      }
+    }
+    nnew += res;
+    if (out) out[i] = (uint8_t)res;
+  }
+  wave_count(t.ctr->size, nnew, (uint32_t)(first / kWave));
+  wave_count(t.ctr->evictions, nevict, (uint32_t)(first / kWave));
+}
+
 // Kernel 3: empty the scratch-set slots the winners of kernel 2 took.  It
 // runs after kernel 2 has finished, so no copy of a key can find its slot
 // empty and win a second time.

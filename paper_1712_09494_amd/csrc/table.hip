@@ -24,6 +24,7 @@ hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, ui
 hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
                         uint32_t, bool, bool, hipStream_t);
 hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, hipStream_t);
+hipError_t cuckoo_single_pass(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
 hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, hipStream_t);
 hipError_t vec_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
                      hipStream_t);
@@ -266,8 +267,10 @@ int validate_config(const ht_config* c) {
   if (c->keys_per_group != 0 && c->keys_per_group != 1 && c->keys_per_group != 2 && c->keys_per_group != 4)
     return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
-                             HT_FLAG_BUCKETED_PAPER_FULL))
+                             HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS))
     return fail(HT_EINVAL, "unknown flag bits");
+  if ((c->flags & HT_FLAG_CUCKOO_SINGLE_PASS) && (c->kind != HT_CUCKOO || c->key_words > 1))
+    return fail(HT_EINVAL, "the single-pass flag is for Cuckoo tables of single-word keys");
   if (c->key_words != 0 && c->key_words != 1 && c->key_words != 2 && c->key_words != 4)
     return fail(HT_EINVAL, "key_words must be 0, 1, 2 or 4");
   if (c->reserved) return fail(HT_EINVAL, "reserved must be 0");
@@ -414,6 +417,12 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     KernelTimer kt("bucketed_fop", s);
     HT_HIP(bucketed_find_or_put(d, keys, n, out, (uint32_t)blocks, R,
                                 (t->cfg.flags & HT_FLAG_CACHED_LOADS) == 0, scripted, s));
+    return HT_OK;
+  }
+  if (t->cfg.flags & HT_FLAG_CUCKOO_SINGLE_PASS) {
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    KernelTimer kt("cuckoo_single_pass", s);
+    HT_HIP(cuckoo_single_pass(d, keys, n, out, (uint32_t)blocks, scripted, s));
     return HT_OK;
   }
   int rc = reserve_scratch(t, n);

@@ -9,7 +9,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import Oracle  # noqa: E402
+from oracle import Oracle, first_occurrence_flags  # noqa: E402
 from paper_1712_09494_amd import binding as b  # noqa: E402
 from paper_1712_09494_amd import inputs  # noqa: E402
 from parity import check_dump_r3, check_flags_r2  # noqa: E402
@@ -183,3 +183,51 @@ def test_large_capacity_no_spill():
     hits0 = sum(pos[k] == t.hash_index(k, 0) for k in keys.tolist())
     assert hits0 >= 3990 and t.stats()["evictions"] == 0
     t.close()
+
+
+def stored_entries(t):
+    """Keys held in slots and stash, counted with repetition."""
+    r = raw(t)
+    return r[r != E]
+
+
+@pytest.mark.parametrize("lf", [0.5, 0.8])
+def test_cuckoo_single_pass_exact_without_repeats(lf):
+    """The paper's single-pass insertion (ablation flag) is exact when no key
+    repeats within a batch: every key new once, stored once."""
+    n = 200000
+    keys = inputs.uniform_keys(n, seed=31)
+    t = b.Table("cuckoo", capacity=int(n / lf), nhash=3, flags=b.HT_FLAG_CUCKOO_SINGLE_PASS)
+    o = Oracle()
+    for part in np.array_split(keys, 4):
+        check_flags_r2(part, b.u64(t.find_or_put(dev(part)).to(torch.int64)).astype(np.uint8),
+                       o.find_or_put(part), f"single pass lf={lf}")
+    s = stored_entries(t)
+    assert s.size == np.unique(s).size == n
+    again = b.u64(t.find_or_put(dev(keys)).to(torch.int64))
+    assert not again.any()
+    t.close()
+
+
+def test_cuckoo_single_pass_with_repeats_keeps_every_key():
+    """With repeated keys the single pass may store a key twice and report it
+    new more than once, but never loses a key, and every distinct new key is
+    reported new at least once.  The three-kernel insertion on the same input
+    stores each key once."""
+    n, d = 400000, 100000
+    keys = inputs.random_sequence(n, d, seed=32)
+    sp = b.Table("cuckoo", capacity=int(d / 0.8), nhash=3, flags=b.HT_FLAG_CUCKOO_SINGLE_PASS)
+    ex = b.Table("cuckoo", capacity=int(d / 0.8), nhash=3)
+    f = b.u64(sp.find_or_put(dev(keys)).to(torch.int64)).astype(np.uint8)
+    assert set(np.unique(f).tolist()) <= {0, 1}
+    assert b.u64(sp.query(dev(keys)).to(torch.int64)).all()
+    new_keys = np.unique(keys[f == 1])
+    assert new_keys.size == d
+    s = stored_entries(sp)
+    assert np.unique(s).size == d and s.size >= d
+    fe = b.u64(ex.find_or_put(dev(keys)).to(torch.int64)).astype(np.uint8)
+    check_flags_r2(keys, fe, first_occurrence_flags(keys), "three kernels")
+    se = stored_entries(ex)
+    assert se.size == np.unique(se).size == d
+    sp.close()
+    ex.close()

@@ -75,9 +75,10 @@ enum {
    * is first written (compare-and-swap) into a candidate slot that the probe
    * saw empty, and the eviction chain starts only when none is left. */
   HT_FLAG_CUCKOO_PAPER_ORDER = 1u << 0,
-  /* Read buckets and slots with ordinary cached loads instead of
-   * device-coherent loads.  Results are identical (a stale empty slot is
-   * corrected by the compare-and-swap result); only the cost differs. */
+  /* Bucketed: read each lane's two slots with one ordinary 16-byte load
+   * instead of two 8-byte agent-scope atomic loads.  Results are identical
+   * (a stale empty slot is corrected by the compare-and-swap result); only
+   * the instruction mix differs (on gfx950 both are plain global loads). */
   HT_FLAG_CACHED_LOADS = 1u << 1,
   /* Test mode: h_j(key) is taken from a table installed with
    * ht_set_scripted_hash instead of the hash family. */
@@ -194,8 +195,8 @@ int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
 typedef struct ht_multi_plan ht_multi_plan;
 
 /* Prepare a many-table find-or-put: validates the arguments, reserves each
- * Cuckoo table's scratch for its batch, and copies the bucketed tables'
- * descriptors and work queue to the device (allocates, synchronises).  The
+ * Cuckoo table's scratch for its batch, and copies the tables' descriptors
+ * and work-item lists to the device (allocates, synchronises).  The
  * key and flag buffers must stay valid for every launch of the plan. */
 int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,

@@ -170,8 +170,11 @@ __device__ __forceinline__ T add_agent(T* p, T v) {
   return __hip_atomic_fetch_add(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
-// Two adjacent 64-bit words (16-byte aligned).  COHERENT reads go to the
-// device coherence point; otherwise an ordinary 16-byte load.
+// Two adjacent 64-bit words (16-byte aligned): two agent-scope atomic 8-byte
+// loads (COHERENT) or one ordinary 16-byte load.  On gfx950 the agent scope
+// adds no cache-control bits to a relaxed load, so the two differ only in
+// load width; correctness never rests on a load being fresh (a stale empty
+// slot is caught by the compare-and-swap result).
 template <bool COHERENT>
 __device__ __forceinline__ void load_pair(const uint64_t* p, uint64_t& a, uint64_t& b) {
   if constexpr (COHERENT) {

@@ -128,7 +128,9 @@ typedef struct {
                               A vector table stores each member once in an
                               arena of (capacity + stash_slots + overflow_slots)
                               entries and keeps 64-bit handles in its slots;
-                              see ht_find_or_put for the key layout */
+                              capacity + stash + overflow below 2^33; batches
+                              below 2^33 vectors; see ht_find_or_put for the
+                              key layout */
   uint32_t reserved;       /* must be 0 */
 } ht_config;
 

@@ -30,6 +30,10 @@ hipError_t vec_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const
                      hipStream_t);
 hipError_t vec_insert(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
                       uint32_t, hipStream_t);
+hipError_t vec_claim(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
+                     hipStream_t);
+hipError_t vec_commit(const DevTable&, const uint64_t*, uint64_t, const CuckooScratch&, uint32_t, uint32_t,
+                      hipStream_t);
 hipError_t vec_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, hipStream_t);
 hipError_t vec_dump(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                     uint32_t, hipStream_t);
@@ -276,8 +280,8 @@ int validate_config(const ht_config* c) {
   if (c->reserved) return fail(HT_EINVAL, "reserved must be 0");
   if (c->key_words > 1) {
     if (c->flags & HT_FLAG_SCRIPTED_HASH) return fail(HT_EINVAL, "scripted hashes need single-word keys");
-    if (c->capacity + 65536ull + (c->overflow_slots ? c->overflow_slots : 65536u) + 64 >= (1ull << kArenaBits) - 1)
-      return fail(HT_EINVAL, "vector table capacity above 2^34 entries");
+    if (c->capacity + 65536ull + (c->overflow_slots ? c->overflow_slots : 65536u) + 64 >= (1ull << (kArenaBits - 1)))
+      return fail(HT_EINVAL, "vector table capacity above 2^33 entries");
   }
   if (c->lds_bytes) {
     int dev = 0, lim = 0;
@@ -390,13 +394,23 @@ static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_
   uint64_t blocks = 0;
   CuckooScratch sc = scratch_view(t, n);
   lane_grid(t, n, 1, blocks, sc.per_wave);
+  const uint32_t W = t->cfg.key_words;
   {
     KernelTimer kt("vec_probe", s);
-    HT_HIP(vec_probe(d, keys, n, out, sc, (uint32_t)blocks, t->cfg.key_words, s));
+    HT_HIP(vec_probe(d, keys, n, out, sc, (uint32_t)blocks, W, s));
+  }
+  if (t->cfg.kind == HT_BUCKETED) {
+    {
+      KernelTimer kt("vec_claim", s);
+      HT_HIP(vec_claim(d, keys, n, out, sc, (uint32_t)blocks, W, s));
+    }
+    KernelTimer kt("vec_commit", s);
+    HT_HIP(vec_commit(d, keys, n, sc, (uint32_t)blocks, W, s));
+    return HT_OK;
   }
   {
     KernelTimer kt("vec_insert", s);
-    HT_HIP(vec_insert(d, keys, n, out, sc, (uint32_t)blocks, t->cfg.key_words, s));
+    HT_HIP(vec_insert(d, keys, n, out, sc, (uint32_t)blocks, W, s));
   }
   {
     KernelTimer kt("vec_scrub", s);
@@ -579,6 +593,8 @@ int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n, uint8_t* d_o
   if (n >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
   if (t->cfg.key_words > 1 && (reinterpret_cast<uintptr_t>(d_keys) & 15))
     return fail(HT_EINVAL, "vector keys must be 16-byte aligned");
+  if (t->cfg.key_words > 1 && n >= (1ull << (kArenaBits - 1)))
+    return fail(HT_EINVAL, "vector batch above 2^33 keys");
   return do_find_or_put(t, d_keys, n, d_out_is_new, s);
 }
 
@@ -736,10 +752,10 @@ int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n, hipStre
     rc = read_counters(t, &h, s);
     if (rc) return rc;
     const uint32_t W = t->cfg.key_words;
-    const uint64_t novf = std::min<uint64_t>(h.overflow_count, t->dev.overflow_slots);
     HT_HIP(vec_dump(t->dev.slots, t->nslots, t->dev.arena, d_out, cap, t->misc, g, W, s));
     HT_HIP(vec_dump(t->dev.stash, t->dev.stash_slots, t->dev.arena, d_out, cap, t->misc, g, W, s));
-    HT_HIP(vec_dump(t->dev.overflow, novf, t->dev.arena, d_out, cap, t->misc, g, W, s));
+    if (h.overflow_count)    // an open-addressed set for vector tables
+      HT_HIP(vec_dump(t->dev.overflow, t->dev.overflow_slots, t->dev.arena, d_out, cap, t->misc, g, W, s));
     unsigned long long nv = 0;
     HT_HIP(hipMemcpyAsync(&nv, t->misc, 8, hipMemcpyDeviceToHost, s));
     HT_HIP(hipStreamSynchronize(s));

@@ -26,6 +26,22 @@ hipError_t vec_insert(const DevTable& t, const uint64_t* keys, uint64_t n, uint8
   return hipGetLastError();
 }
 
+hipError_t vec_claim(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
+                     uint32_t grid, uint32_t W, hipStream_t st) {
+#define HT_L(WW) hipLaunchKernelGGL((vec_claim_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
+  HT_W_DISPATCH(HT_L)
+#undef HT_L
+  return hipGetLastError();
+}
+
+hipError_t vec_commit(const DevTable& t, const uint64_t* keys, uint64_t n, const CuckooScratch& s, uint32_t grid,
+                      uint32_t W, hipStream_t st) {
+#define HT_L(WW) hipLaunchKernelGGL((vec_commit_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, s)
+  HT_W_DISPATCH(HT_L)
+#undef HT_L
+  return hipGetLastError();
+}
+
 hipError_t vec_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid, uint32_t W,
                      hipStream_t st) {
 #define HT_L(WW) hipLaunchKernelGGL((vec_query_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out)

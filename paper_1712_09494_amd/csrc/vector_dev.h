@@ -11,18 +11,32 @@
 // the arena.  A handle is never all ones (arena indices stay below 2^34 - 1),
 // so the empty marker needs no special key.
 //
-// Find-or-put in three kernels, like the single-word Cuckoo table:
+// Find-or-put in three kernels; the first is the same for both designs:
 //   1. lookup (read-only): compare hash bits, then the arena words; vectors
-//      found report 0, the others are listed with their hash;
+//      found report 0, the others are listed with their hash.
+// Bucketed tables, where a handle never moves once placed:
+//   2. claim: each listed vector walks its bucket sequence (then the stash,
+//      then the overflow set) and compare-and-swaps a placeholder -- its hash
+//      bits and its batch index -- into the first empty slot.  Copies of a
+//      vector walk the same slots in the same order, so a second copy meets
+//      the first one's placeholder and compares the two batch rows (complete
+//      before the kernel starts): equal means it reports 0.  One atomic per
+//      listed vector, no scratch set;
+//   3. commit: each claimed slot takes an arena entry (one counter atomic per
+//      wave), gets the vector's words written there and its placeholder
+//      replaced by the final handle.  No other lane touches that slot in this
+//      kernel, and lookups run only in later kernels.
+// Cuckoo tables, where exchanges move handles (a placeholder could not be
+// found again):
 //   2. insert: the listed vectors are deduplicated in the scratch set by
 //      batch index (equal vectors compared word by word in the batch); each
-//      winner reports 1, takes an arena entry (one counter atomic per wave),
-//      writes its words and places its handle: bucketed -- lowest empty slot
-//      along the bucket sequence; Cuckoo -- first empty candidate slot, else
-//      the exchange chain of Sec. 4.1 from h_1; then stash, overflow list.
-//      Winners are distinct and absent, so placing needs no comparison and
-//      nothing in this kernel reads a vector another lane is writing;
+//      winner reports 1, takes an arena entry, writes its words and places
+//      its handle -- first empty candidate slot, else the exchange chain of
+//      Sec. 4.1 from h_1 -- then stash, overflow set.  Winners are distinct
+//      and absent, so placing needs no comparison;
 //   3. scrub the scratch set (the single-word Cuckoo scrub kernel).
+// The stash and the overflow list of a vector table are open-addressed sets
+// of handles, probed from positions given by the hash bits.
 // Lookups stop early by the same rules as the single-word tables: a bucket
 // with an empty slot ends the bucket sequence (slots fill as a prefix and are
 // never emptied), and a Cuckoo lookup stops at an empty candidate when the
@@ -33,6 +47,10 @@
 namespace ht {
 
 constexpr uint64_t kArenaMask = (1ull << kArenaBits) - 1;
+// Arena indices stay below 2^33; bit 33 of a handle marks a placeholder whose
+// low 33 bits are a batch index (bucketed claim kernel, replaced in commit).
+constexpr uint64_t kPlaceBit = 1ull << 33;
+constexpr uint64_t kBatchMask = kPlaceBit - 1;
 
 // Hash of a vector: the words folded through mix64 in order, seeded per table.
 template <int W>
@@ -65,10 +83,11 @@ __device__ __forceinline__ bool vec_eq(const uint64_t (&a)[W], const uint64_t (&
   return e;
 }
 
-// Handle hd holds vector v: hash bits first, then the arena words.
+// Handle hd holds vector v: hash bits first, then the arena words.  Empty
+// slots and placeholders hold no arena entry.
 template <int W>
 __device__ __forceinline__ bool vec_holds(const DevTable& t, uint64_t hd, uint64_t hb, const uint64_t (&v)[W]) {
-  if (hd == kEmpty || handle_hb(hd) != hb) return false;
+  if (hd == kEmpty || (hd & kPlaceBit) || handle_hb(hd) != hb) return false;
   uint64_t a[W];
   load_vec<W>(t.arena + handle_idx(hd) * W, a);
   return vec_eq<W>(a, v);
@@ -81,6 +100,17 @@ __device__ __forceinline__ uint64_t vec_bucket(const DevTable& t, uint64_t hb, u
   return prev + 1 == t.nrange ? 0 : prev + 1;
 }
 
+// Eight consecutive slots (64-byte aligned: bucket widths are multiples of
+// 8 slots), four independent 16-byte loads in flight together.
+__device__ __forceinline__ void load8(const uint64_t* p, uint64_t (&x)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(p + k);
+    x[k] = y.x;
+    x[k + 1] = y.y;
+  }
+}
+
 template <int W>
 __device__ bool vec_lookup_bucketed(const DevTable& t, uint64_t hb, const uint64_t (&v)[W]) {
   const uint32_t B = t.bucket_slots;
@@ -89,12 +119,14 @@ __device__ bool vec_lookup_bucketed(const DevTable& t, uint64_t hb, const uint64
   for (uint32_t q = 0; q < steps; ++q) {
     b = vec_bucket(t, hb, q, b);
     const uint64_t* bk = t.slots + b * B;
-    for (uint32_t s = 0; s < B; s += 2) {
-      const ulonglong2 x = *reinterpret_cast<const ulonglong2*>(bk + s);
-      if (x.x == kEmpty) return false;          // prefix: the rest of the sequence is unused
-      if (vec_holds<W>(t, x.x, hb, v)) return true;
-      if (x.y == kEmpty) return false;
-      if (vec_holds<W>(t, x.y, hb, v)) return true;
+    for (uint32_t c0 = 0; c0 < B; c0 += 8) {
+      uint64_t x[8];
+      load8(bk + c0, x);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        if (x[k] == kEmpty) return false;       // prefix: the rest of the sequence is unused
+        if (vec_holds<W>(t, x[k], hb, v)) return true;
+      }
     }
   }
   return false;
@@ -114,7 +146,12 @@ __device__ bool vec_lookup_cuckoo(const DevTable& t, uint64_t hb, const uint64_t
   return false;
 }
 
-// Stash (positions from the hash bits, linear probing) and overflow list.
+// Start of the overflow set's probe sequence (linear probing, any length).
+__device__ __forceinline__ uint32_t overflow_start(const DevTable& t, uint64_t hb) {
+  return (uint32_t)mulhi64(mix64(hb ^ t.stash_seed ^ 0x5851f42d4c957f2dull), t.overflow_slots);
+}
+
+// Stash and overflow set: probe from the hash bits' position until an empty slot.
 template <int W>
 __device__ bool vec_stash_query(const DevTable& t, uint64_t hb, const uint64_t (&v)[W], uint32_t sc,
                                 uint32_t oc) {
@@ -129,9 +166,14 @@ __device__ bool vec_stash_query(const DevTable& t, uint64_t hb, const uint64_t (
     }
   }
   if (oc) {
-    const uint32_t m = oc < t.overflow_slots ? oc : t.overflow_slots;
-    for (uint32_t i = 0; i < m; ++i)
-      if (vec_holds<W>(t, t.overflow[i], hb, v)) return true;
+    const uint32_t m = t.overflow_slots;
+    uint32_t p = overflow_start(t, hb);
+    for (uint32_t i = 0; i < m; ++i) {
+      const uint64_t hd = t.overflow[p];
+      if (hd == kEmpty) break;
+      if (vec_holds<W>(t, hd, hb, v)) return true;
+      p = p + 1 == m ? 0 : p + 1;
+    }
   }
   return false;
 }
@@ -154,26 +196,16 @@ __device__ inline void vec_stash_put(const DevTable& t, uint64_t hd) {
     }
     p = (p + 1) & (S - 1);
   }
-  const uint32_t pos = add_agent(&t.ctr->overflow_count, 1u);
-  if (pos < t.overflow_slots)
-    store_coherent(&t.overflow[pos], hd);
-  else
-    add_agent(&t.ctr->lost, 1u);
-}
-
-__device__ inline void vec_place_bucketed(const DevTable& t, uint64_t hd) {
-  const uint64_t hb = handle_hb(hd);
-  const uint32_t B = t.bucket_slots;
-  const uint32_t steps = t.nhash + t.walk;
-  uint64_t b = 0;
-  for (uint32_t q = 0; q < steps; ++q) {
-    b = vec_bucket(t, hb, q, b);
-    uint64_t* bk = t.slots + b * B;
-    // lowest empty slot first; a lost race moves on to the next slot
-    for (uint32_t s = 0; s < B; ++s)
-      if (bk[s] == kEmpty && cas64(&bk[s], kEmpty, hd) == kEmpty) return;
+  const uint32_t m = t.overflow_slots;
+  p = overflow_start(t, handle_hb(hd));
+  for (uint32_t i = 0; i < m; ++i) {
+    if (cas64(&t.overflow[p], kEmpty, hd) == kEmpty) {
+      add_agent(&t.ctr->overflow_count, 1u);
+      return;
+    }
+    p = p + 1 == m ? 0 : p + 1;
   }
-  vec_stash_put(t, hd);
+  add_agent(&t.ctr->lost, 1u);
 }
 
 __device__ inline void vec_place_cuckoo(const DevTable& t, uint64_t hd, unsigned long long& nevict) {
@@ -204,6 +236,28 @@ __device__ inline void vec_place_cuckoo(const DevTable& t, uint64_t hd, unsigned
     slot = h[nj];
   }
   vec_stash_put(t, x);
+}
+
+// Arena entries for the lanes with `want` set: one counter atomic per wave
+// and range.  A wave starts at its own range and moves on while a range is
+// full, so every entry of every range is handed out.  ~0 when all are taken.
+__device__ inline uint64_t arena_take(const DevTable& t, bool want, uint64_t wave) {
+  uint64_t idx = ~0ull;
+  for (uint32_t a = 0; a < (uint32_t)kSpread; ++a) {
+    const uint64_t wm = ballot(want);
+    if (!wm) break;
+    const uint32_t rg = (uint32_t)((wave + a) % kSpread);
+    unsigned long long first = 0;
+    if (lane_id() == 0) first = add_agent(&t.ctr->arena_next[rg * kLineWords], (unsigned long long)__popcll(wm));
+    first = shfl64(first, 0);
+    const uint64_t avail = first < t.arena_cap ? t.arena_cap - first : 0;
+    const uint64_t rank = lanes_below(wm);
+    if (want && rank < avail) {
+      idx = (uint64_t)rg * t.arena_cap + first + rank;
+      want = false;
+    }
+  }
+  return idx;
 }
 
 // Kernel 1: lookup; misses listed per wave region as (hash, batch index).
@@ -244,8 +298,8 @@ __global__ __launch_bounds__(kBlock) void vec_probe_kernel(DevTable t, const uin
   if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
 }
 
-// Kernel 2: deduplicate the listed vectors, store the winners and place their
-// handles.  Each pass of the wave takes up to 64 listed vectors.
+// Kernel 2 (Cuckoo): deduplicate the listed vectors, store the winners and
+// place their handles.  Each pass of the wave takes up to 64 listed vectors.
 template <int W>
 __global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                              uint64_t n, uint8_t* __restrict__ out,
@@ -284,24 +338,7 @@ __global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const ui
       s.wmeta[begin + e] = winner ? p : ~0ull;   // scratch-set slot for the scrub kernel
     }
     if (!ballot(winner)) continue;
-    // arena entries: one counter atomic per wave and range; a wave starts at
-    // its own range and moves on while a range is full
-    uint64_t idx = ~0ull;
-    bool want = winner;
-    for (uint32_t a = 0; a < (uint32_t)kSpread; ++a) {
-      const uint64_t wm = ballot(want);
-      if (!wm) break;
-      const uint32_t rg = (uint32_t)((wave + a) % kSpread);
-      unsigned long long first = 0;
-      if (lane == 0) first = add_agent(&t.ctr->arena_next[rg * kLineWords], (unsigned long long)__popcll(wm));
-      first = shfl64(first, 0);
-      const uint64_t avail = first < t.arena_cap ? t.arena_cap - first : 0;
-      const uint64_t rank = lanes_below(wm);
-      if (want && rank < avail) {
-        idx = (uint64_t)rg * t.arena_cap + first + rank;
-        want = false;
-      }
-    }
+    const uint64_t idx = arena_take(t, winner, wave);
     if (winner) {
       ++nnew;
       if (idx == ~0ull) {
@@ -310,16 +347,146 @@ __global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const ui
 #pragma unroll
         for (int j = 0; j < W; j += 2)
           *reinterpret_cast<ulonglong2*>(t.arena + idx * W + j) = make_ulonglong2(v[j], v[j + 1]);
-        const uint64_t hd = ((H >> kArenaBits) << kArenaBits) | idx;
-        if (t.kind == HT_KIND_BUCKETED)
-          vec_place_bucketed(t, hd);
-        else
-          vec_place_cuckoo(t, hd, nevict);
+        vec_place_cuckoo(t, ((H >> kArenaBits) << kArenaBits) | idx, nevict);
       }
     }
   }
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
+}
+
+// One slot of a claim walk, given the value read there: 1 = the placeholder
+// is now here, 2 = an equal vector of the batch holds this slot, 0 = go on.
+template <int W>
+__device__ __forceinline__ int vec_claim_seen(uint64_t* p, uint64_t hd, uint64_t ph, uint64_t hb,
+                                              const uint64_t (&v)[W], const uint64_t* __restrict__ keys,
+                                              uint64_t n) {
+  if (hd == kEmpty) {
+    hd = cas64(p, kEmpty, ph);
+    if (hd == kEmpty) return 1;
+  }
+  if ((hd & kPlaceBit) && hd != kEmpty && handle_hb(hd) == hb) {
+    const uint64_t j = hd & kBatchMask;
+    if (j < n) {
+      uint64_t u[W];
+      load_vec<W>(keys + j * W, u);
+      if (vec_eq<W>(u, v)) return 2;
+    }
+  }
+  return 0;
+}
+
+template <int W>
+__device__ __forceinline__ int vec_claim_slot(uint64_t* p, uint64_t ph, uint64_t hb, const uint64_t (&v)[W],
+                                              const uint64_t* __restrict__ keys, uint64_t n) {
+  return vec_claim_seen<W>(p, *p, ph, hb, v, keys, n);
+}
+
+// Kernel 2 (bucketed): claim a slot per distinct listed vector.  Locations
+// are numbered slots, then stash, then overflow set; the list entry becomes
+// (claimed location or ~0, hash bits << 33 | batch index) for the commit
+// kernel.
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_claim_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,
+                                                            uint8_t* __restrict__ out, CuckooScratch s) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint64_t begin = wave * s.per_wave;
+  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
+  const uint32_t B = t.bucket_slots;
+  const uint32_t steps = t.nhash + t.walk;
+  const uint64_t nslots = t.nrange * B;
+  unsigned long long nnew = 0;
+  for (uint32_t e = (uint32_t)lane_id(); e < cnt; e += kWave) {
+    const uint64_t H = s.wkey[begin + e];
+    const uint64_t i = s.wmeta[begin + e];
+    uint64_t v[W];
+    load_vec<W>(keys + i * W, v);
+    const uint64_t hb = H >> kArenaBits;
+    const uint64_t ph = (hb << kArenaBits) | kPlaceBit | i;
+    int st = 0;
+    uint64_t loc = ~0ull;
+    uint64_t b = 0;
+    for (uint32_t q = 0; q < steps && !st; ++q) {
+      b = vec_bucket(t, hb, q, b);
+      for (uint32_t c0 = 0; c0 < B && !st; c0 += 8) {
+        uint64_t x[8];
+        load8(t.slots + b * B + c0, x);
+        for (uint32_t k = 0; k < 8 && !st; ++k) {
+          st = vec_claim_seen<W>(t.slots + b * B + c0 + k, x[k], ph, hb, v, keys, n);
+          if (st == 1) loc = b * B + c0 + k;
+        }
+      }
+    }
+    if (!st) {
+      const uint32_t S = t.stash_slots;
+      uint32_t p = stash_start(t, hb);
+      for (uint32_t k = 0; k < S && !st; ++k) {
+        st = vec_claim_slot<W>(t.stash + p, ph, hb, v, keys, n);
+        if (st == 1) {
+          loc = nslots + p;
+          add_agent(&t.ctr->stash_count, 1u);
+        }
+        p = (p + 1) & (S - 1);
+      }
+    }
+    if (!st) {
+      const uint32_t m = t.overflow_slots;
+      uint32_t p = overflow_start(t, hb);
+      for (uint32_t k = 0; k < m && !st; ++k) {
+        st = vec_claim_slot<W>(t.overflow + p, ph, hb, v, keys, n);
+        if (st == 1) {
+          loc = nslots + t.stash_slots + p;
+          add_agent(&t.ctr->overflow_count, 1u);
+        }
+        p = p + 1 == m ? 0 : p + 1;
+      }
+    }
+    if (!st) add_agent(&t.ctr->lost, 1u);
+    const uint32_t res = st == 2 ? 0u : 1u;
+    nnew += res;
+    if (out) out[i] = (uint8_t)res;
+    s.wkey[begin + e] = loc;                     // for the commit kernel: where, and
+    s.wmeta[begin + e] = (hb << 33) | i;         // which vector with which hash bits
+  }
+  wave_count(t.ctr->size, nnew, (uint32_t)wave);
+}
+
+__device__ __forceinline__ uint64_t* vec_location(const DevTable& t, uint64_t loc) {
+  const uint64_t nslots = t.nrange * t.bucket_slots;
+  if (loc < nslots) return t.slots + loc;
+  loc -= nslots;
+  if (loc < t.stash_slots) return t.stash + loc;
+  return t.overflow + (loc - t.stash_slots);
+}
+
+// Kernel 3 (bucketed): the claimed slots get arena entries, the vectors'
+// words and their final handles.
+template <int W>
+__global__ __launch_bounds__(kBlock) void vec_commit_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,
+                                                             CuckooScratch s) {
+  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const uint64_t begin = wave * s.per_wave;
+  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
+  for (uint32_t e0 = 0; e0 < cnt; e0 += kWave) {
+    const uint32_t e = e0 + (uint32_t)lane_id();
+    const uint64_t loc = e < cnt ? s.wkey[begin + e] : ~0ull;
+    const bool have = loc != ~0ull;
+    if (!ballot(have)) continue;
+    const uint64_t idx = arena_take(t, have, wave);
+    if (!have) continue;
+    if (idx == ~0ull) {
+      add_agent(&t.ctr->lost, 1u);               // cannot happen: every claimed location has an entry
+      continue;
+    }
+    const uint64_t m = s.wmeta[begin + e];
+    const uint64_t i = m & kBatchMask;
+    uint64_t v[W];
+    load_vec<W>(keys + i * W, v);
+#pragma unroll
+    for (int j = 0; j < W; j += 2)
+      *reinterpret_cast<ulonglong2*>(t.arena + idx * W + j) = make_ulonglong2(v[j], v[j + 1]);
+    store_coherent(vec_location(t, loc), ((m >> 33) << kArenaBits) | idx);
+  }
 }
 
 template <int W>
@@ -347,7 +514,7 @@ __global__ __launch_bounds__(kBlock) void vec_dump_kernel(const uint64_t* __rest
   for (uint64_t base = (uint64_t)blockIdx.x * kBlock + (threadIdx.x & ~63u); base < nh; base += stride) {
     const uint64_t i = base + lane;
     const uint64_t hd = i < nh ? handles[i] : kEmpty;
-    const bool keep = hd != kEmpty;
+    const bool keep = hd != kEmpty && !(hd & kPlaceBit);
     const uint64_t m = ballot(keep);
     if (!m) continue;
     unsigned long long b = 0;

@@ -32,7 +32,7 @@ GRID = {
     "cuckoo": [dict(nhash=c, keys_per_group=R) for c in (2, 3, 4) for R in (1, 2, 4)],
 }
 
-# the paper's table settings (c about 4, size 1.25 n) as a fallback point
+# fallback when a shape has not been measured: one 128-byte line per bucket, c = 3
 DEFAULT = {"bucketed": dict(bucket_slots=16, nhash=3, keys_per_group=2),
            "cuckoo": dict(nhash=3, keys_per_group=2)}
 

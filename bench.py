@@ -182,11 +182,22 @@ def main():
             evs.append((e0, e1))
         torch.cuda.synchronize()
         lat = np.array([a.elapsed_time(c) for a, c in evs])
+        # least bytes a find-or-put of the batch must move, either design: key + flag +
+        # one slot line per key, a dirtied half-line per new key
+        nb = (args.n + args.batch - 1) // args.batch
+        least = (args.n * (9 + LINE) + d * HALF) / nb
+        mean_s = float(lat.mean()) * 1e-3
+        kernels = {"bucketed": ["bucketed_fop"],
+                   "cuckoo": ["cuckoo_probe", "cuckoo_evict", "cuckoo_scrub"]}[name]
+        traffic = [measured_traffic(k) if (args.batch == 1 << 20 and args.n == 1 << 26) else None for k in kernels]
         per_design[name] = {
             "mops": round(args.n / lat.sum() / 1e3, 1),
             "batch_ms_p50": round(float(np.percentile(lat, 50)), 4),
             "batch_ms_p99": round(float(np.percentile(lat, 99)), 4),
             "ms_total": round(float(lat.sum()), 3),
+            "hbm_frac_least_bytes": round(least / mean_s / 1e9 / HBM_PEAK_GBS, 4),
+            "hbm_frac_measured": (round(sum(traffic) / mean_s / 1e9 / HBM_PEAK_GBS, 4)
+                                  if all(x is not None for x in traffic) else None),
         }
     b.ht_timing_enable(True)
     for name in designs:

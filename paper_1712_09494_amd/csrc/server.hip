@@ -51,6 +51,11 @@ class StagingPool {
     free_.assign(1, {0, bytes});
     return HT_OK;
   }
+  // Every block free again (a run starts with nothing in flight).
+  void reset() {
+    free_.assign(1, {0, size_});
+    used_ = 0;
+  }
   void release_all() {
     if (base_) (void)hipFree(base_);
     base_ = nullptr;
@@ -204,6 +209,17 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
     if (r.op == HT_OP_FIND_OR_PUT) need[r.table] = std::max(need[r.table], r.n);
   }
   if (max_stage > s->pool.size()) return fail(HT_ENOMEM, "a request needs more staging than the server's budget");
+  // a run starts with nothing in flight, also after an earlier run stopped on an error
+  {
+    hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+  }
+  s->pool.reset();
+  for (auto& sl : s->slots) {
+    sl.reqs.clear();
+    sl.offs.clear();
+    sl.busy = false;
+  }
   // everything that allocates happens before the clock starts
   for (uint32_t t = 0; t < nt; ++t)
     if (s->tables[t]->cfg.kind == HT_CUCKOO && need[t]) {

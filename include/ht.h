@@ -106,7 +106,8 @@ typedef struct {
                               line of 64-bit keys).  Ignored by cuckoo */
   uint32_t keys_per_group; /* keys each lane group (bucketed) or lane (cuckoo)
                               keeps in flight: 1, 2 or 4; 0 = by design
-                              (bucketed B=8: 1, B=16: 2, B>=32: 4; cuckoo: 1) */
+                              (bucketed B=8: 1, B=16: 2, B>=32: 4; cuckoo: 1).
+                              Bucketed queries use at least 2 */
   uint32_t stash_slots;    /* stash size (power of two, <= 65536); 0 = 1024 */
   uint32_t max_chain;      /* cuckoo eviction bound; 0 = 8 * ceil(log2 capacity) */
   uint64_t seed;           /* seed of the hash constants */

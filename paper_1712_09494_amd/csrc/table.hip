@@ -473,11 +473,14 @@ int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStr
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
   if (t->cfg.kind == HT_BUCKETED) {
-    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R);
+    // a query issues no atomics, so a second key in flight per group pays off
+    // even where find-or-put prefers one (measured: +11-14% at B = 8 and 16)
+    const uint32_t Rq = R < 2 ? 2 : R;
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, Rq);
     const uint64_t waves = (n + g - 1) / g;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_query", s);
-    HT_HIP(bucketed_query(d, keys, n, out, (uint32_t)blocks, R, scripted, s));
+    HT_HIP(bucketed_query(d, keys, n, out, (uint32_t)blocks, Rq, scripted, s));
   } else {
     const uint64_t per = (uint64_t)kBlock * R;
     const uint64_t blocks = std::min<uint64_t>((n + per - 1) / per, max_blocks(t));

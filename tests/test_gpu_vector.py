@@ -164,3 +164,28 @@ def test_vec_rejected_uses():
     t.clear()
     assert t.size() == 0 and t.dump().shape[0] == 0
     t.close()
+
+
+@pytest.mark.parametrize("kind", ["bucketed", "cuckoo"])
+@pytest.mark.parametrize("w", [2, 4])
+def test_vec_random_small_tables(kind, w):
+    """Random small tables (64..1024 slots, c = 1..4, any bucket width), pools of
+    vectors that share words, several batches with repeats: flags, queries and
+    dump against the oracle, through spills into the stash and overflow set."""
+    rng = np.random.default_rng(100 + w + (kind == "cuckoo"))
+    for trial in range(10):
+        cap = int(rng.choice([64, 128, 256, 1024]))
+        kw = dict(bucket_slots=int(rng.choice([8, 16, 32, 64]))) if kind == "bucketed" else {}
+        t = b.Table(kind, capacity=cap, nhash=int(rng.integers(1, 5)), stash_slots=32, overflow_slots=2048,
+                    key_words=w, **kw)
+        o = VecOracle(w)
+        pool = inputs.vector_of_index(np.arange(int(rng.integers(8, 2 * cap))), w, seed=trial,
+                                      structured=bool(trial % 2))
+        for _ in range(4):
+            part = pool[rng.integers(0, len(pool), size=int(rng.integers(0, 900)))]
+            check_flags(part, fop(t, part), o.find_or_put(part), w, f"{kind} w={w} trial {trial} cap {cap}")
+        extra = inputs.vector_of_index(np.arange(10 ** 6, 10 ** 6 + 50), w, seed=trial)
+        q = np.concatenate([pool, extra])
+        assert (query(t, q) == o.query(q)).all(), f"{kind} trial {trial}"
+        check_dump(t, o, w, f"{kind} trial {trial}")
+        t.close()

@@ -28,7 +28,7 @@ hipError_t cuckoo_single_pass(const DevTable&, const uint64_t*, uint64_t, uint8_
 hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, hipStream_t);
 hipError_t vec_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
                      hipStream_t);
-hipError_t vec_insert(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
+hipError_t vec_evict(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
                       uint32_t, hipStream_t);
 hipError_t vec_claim(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
                      hipStream_t);
@@ -399,18 +399,19 @@ static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_
     KernelTimer kt("vec_probe", s);
     HT_HIP(vec_probe(d, keys, n, out, sc, (uint32_t)blocks, W, s));
   }
-  if (t->cfg.kind == HT_BUCKETED) {
-    {
-      KernelTimer kt("vec_claim", s);
-      HT_HIP(vec_claim(d, keys, n, out, sc, (uint32_t)blocks, W, s));
-    }
-    KernelTimer kt("vec_commit", s);
-    HT_HIP(vec_commit(d, keys, n, sc, (uint32_t)blocks, W, s));
-    return HT_OK;
+  {
+    KernelTimer kt("vec_claim", s);
+    HT_HIP(vec_claim(d, keys, n, out, sc, (uint32_t)blocks, W, s));
   }
   {
-    KernelTimer kt("vec_insert", s);
-    HT_HIP(vec_insert(d, keys, n, out, sc, (uint32_t)blocks, W, s));
+    KernelTimer kt("vec_commit", s);
+    HT_HIP(vec_commit(d, keys, n, sc, (uint32_t)blocks, W, s));
+  }
+  if (t->cfg.kind == HT_BUCKETED) return HT_OK;
+  // Cuckoo: vectors whose candidates were all taken run the eviction chain
+  {
+    KernelTimer kt("vec_evict", s);
+    HT_HIP(vec_evict(d, keys, n, out, sc, (uint32_t)blocks, W, s));
   }
   {
     KernelTimer kt("vec_scrub", s);

@@ -18,9 +18,9 @@ hipError_t vec_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_
   return hipGetLastError();
 }
 
-hipError_t vec_insert(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
+hipError_t vec_evict(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
                       uint32_t grid, uint32_t W, hipStream_t st) {
-#define HT_L(WW) hipLaunchKernelGGL((vec_insert_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
+#define HT_L(WW) hipLaunchKernelGGL((vec_evict_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
   HT_W_DISPATCH(HT_L)
 #undef HT_L
   return hipGetLastError();

@@ -11,30 +11,27 @@
 // the arena.  A handle is never all ones (arena indices stay below 2^34 - 1),
 // so the empty marker needs no special key.
 //
-// Find-or-put in three kernels; the first is the same for both designs:
+// Find-or-put, with no kernel reading a vector another lane is still writing
+// and no lane waiting for another:
 //   1. lookup (read-only): compare hash bits, then the arena words; vectors
-//      found report 0, the others are listed with their hash.
-// Bucketed tables, where a handle never moves once placed:
-//   2. claim: each listed vector walks its bucket sequence (then the stash,
-//      then the overflow set) and compare-and-swaps a placeholder -- its hash
-//      bits and its batch index -- into the first empty slot.  Copies of a
-//      vector walk the same slots in the same order, so a second copy meets
-//      the first one's placeholder and compares the two batch rows (complete
-//      before the kernel starts): equal means it reports 0.  One atomic per
-//      listed vector, no scratch set;
+//      found report 0, the others are listed with their hash;
+//   2. claim: each listed vector compare-and-swaps a placeholder -- its hash
+//      bits and its batch index -- into the first empty slot of its bucket
+//      sequence (then stash, then overflow set) or, in a Cuckoo table, of its
+//      candidate slots h_1..h_c.  Copies of a vector walk the same slots in
+//      the same order, so a second copy meets the first one's placeholder and
+//      compares the two batch rows (complete before the kernel starts): equal
+//      means it reports 0.  No exchange runs in this kernel, so placeholders
+//      stay where they were put.  One atomic per listed vector;
 //   3. commit: each claimed slot takes an arena entry (one counter atomic per
 //      wave), gets the vector's words written there and its placeholder
-//      replaced by the final handle.  No other lane touches that slot in this
-//      kernel, and lookups run only in later kernels.
-// Cuckoo tables, where exchanges move handles (a placeholder could not be
-// found again):
-//   2. insert: the listed vectors are deduplicated in the scratch set by
-//      batch index (equal vectors compared word by word in the batch); each
-//      winner reports 1, takes an arena entry, writes its words and places
-//      its handle -- first empty candidate slot, else the exchange chain of
-//      Sec. 4.1 from h_1 -- then stash, overflow set.  Winners are distinct
-//      and absent, so placing needs no comparison;
-//   3. scrub the scratch set (the single-word Cuckoo scrub kernel).
+//      replaced by the final handle;
+// and for Cuckoo tables, the vectors that found every candidate taken:
+//   4. evict: deduplicated in the scratch set by batch index (equal vectors
+//      compared word by word in the batch); each winner reports 1, takes an
+//      arena entry, writes its words and runs the exchange chain of Sec. 4.1
+//      from h_1 with its handle (then stash, overflow set);
+//   5. scrub the scratch set (the single-word Cuckoo scrub kernel).
 // The stash and the overflow list of a vector table are open-addressed sets
 // of handles, probed from positions given by the hash bits.
 // Lookups stop early by the same rules as the single-word tables: a bucket
@@ -298,12 +295,19 @@ __global__ __launch_bounds__(kBlock) void vec_probe_kernel(DevTable t, const uin
   if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
 }
 
-// Kernel 2 (Cuckoo): deduplicate the listed vectors, store the winners and
-// place their handles.  Each pass of the wave takes up to 64 listed vectors.
+// List entry of a vector whose Cuckoo candidates were all taken at claim
+// time: it goes to the evict kernel.
+constexpr uint64_t kLeftover = ~1ull;
+
+// Kernel 4 (Cuckoo): the leftover vectors are deduplicated in the scratch
+// set by batch index (equal vectors compared word by word in the batch);
+// each winner reports 1, takes an arena entry, writes its words and runs the
+// exchange chain of Sec. 4.1 from h_1 with its handle.  Every list entry's
+// meta word becomes its scratch-set slot (or ~0) for the scrub kernel.
 template <int W>
-__global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const uint64_t* __restrict__ keys,
-                                                             uint64_t n, uint8_t* __restrict__ out,
-                                                             CuckooScratch s) {
+__global__ __launch_bounds__(kBlock) void vec_evict_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                            uint64_t n, uint8_t* __restrict__ out,
+                                                            CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const int lane = lane_id();
   const uint64_t begin = wave * s.per_wave;
@@ -312,30 +316,35 @@ __global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const ui
   for (uint32_t e0 = 0; e0 < cnt; e0 += kWave) {
     const uint32_t e = e0 + (uint32_t)lane;
     bool winner = false;
-    uint64_t H = 0;
+    uint64_t hb = 0;
     uint64_t v[W];
 #pragma unroll
     for (int j = 0; j < W; ++j) v[j] = 0;
     if (e < cnt) {
-      H = s.wkey[begin + e];
-      const uint64_t i = s.wmeta[begin + e];
-      load_vec<W>(keys + i * W, v);
-      uint64_t p = mix64(H ^ s.dset_seed) & s.dset_mask;
-      for (;;) {
-        const uint64_t old = cas64(&s.dset[p], kEmpty, i);
-        if (old == kEmpty) {
-          winner = true;
-          break;
+      uint64_t p = ~0ull;
+      if (s.wkey[begin + e] == kLeftover) {
+        const uint64_t m = s.wmeta[begin + e];
+        const uint64_t i = m & kBatchMask;
+        hb = m >> 33;
+        load_vec<W>(keys + i * W, v);
+        p = mix64(hb ^ s.dset_seed) & s.dset_mask;
+        for (;;) {
+          const uint64_t old = cas64(&s.dset[p], kEmpty, i);
+          if (old == kEmpty) {
+            winner = true;
+            break;
+          }
+          if (old < n) {                   // the set holds indices of this batch only
+            uint64_t u[W];
+            load_vec<W>(keys + old * W, u);
+            if (vec_eq<W>(u, v)) break;    // an equal vector of the batch won
+          }
+          p = (p + 1) & s.dset_mask;
         }
-        if (old < n) {                     // the set holds indices of this batch only
-          uint64_t u[W];
-          load_vec<W>(keys + old * W, u);
-          if (vec_eq<W>(u, v)) break;      // an equal vector of the batch won
-        }
-        p = (p + 1) & s.dset_mask;
+        if (out) out[i] = winner ? 1 : 0;
+        if (!winner) p = ~0ull;
       }
-      if (out) out[i] = winner ? 1 : 0;
-      s.wmeta[begin + e] = winner ? p : ~0ull;   // scratch-set slot for the scrub kernel
+      s.wmeta[begin + e] = p;
     }
     if (!ballot(winner)) continue;
     const uint64_t idx = arena_take(t, winner, wave);
@@ -347,7 +356,7 @@ __global__ __launch_bounds__(kBlock) void vec_insert_kernel(DevTable t, const ui
 #pragma unroll
         for (int j = 0; j < W; j += 2)
           *reinterpret_cast<ulonglong2*>(t.arena + idx * W + j) = make_ulonglong2(v[j], v[j + 1]);
-        vec_place_cuckoo(t, ((H >> kArenaBits) << kArenaBits) | idx, nevict);
+        vec_place_cuckoo(t, (hb << kArenaBits) | idx, nevict);
       }
     }
   }
@@ -382,10 +391,13 @@ __device__ __forceinline__ int vec_claim_slot(uint64_t* p, uint64_t ph, uint64_t
   return vec_claim_seen<W>(p, *p, ph, hb, v, keys, n);
 }
 
-// Kernel 2 (bucketed): claim a slot per distinct listed vector.  Locations
-// are numbered slots, then stash, then overflow set; the list entry becomes
-// (claimed location or ~0, hash bits << 33 | batch index) for the commit
-// kernel.
+// Kernel 2: claim a slot per distinct listed vector.  Bucketed: along the
+// bucket sequence, then stash, then overflow set.  Cuckoo: among the empty
+// candidate slots h_1..h_c only (no exchange runs in this kernel, so
+// placeholders stay put); a vector that finds every candidate taken is left
+// for the evict kernel.  Locations are numbered slots, then stash, then
+// overflow set; the list entry becomes (claimed location, ~0 for a copy of
+// a claimed vector or kLeftover, hash bits << 33 | batch index).
 template <int W>
 __global__ __launch_bounds__(kBlock) void vec_claim_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,
                                                             uint8_t* __restrict__ out, CuckooScratch s) {
@@ -405,6 +417,24 @@ __global__ __launch_bounds__(kBlock) void vec_claim_kernel(DevTable t, const uin
     const uint64_t ph = (hb << kArenaBits) | kPlaceBit | i;
     int st = 0;
     uint64_t loc = ~0ull;
+    if (t.kind == HT_KIND_CUCKOO) {
+      for (uint32_t j = 0; j < t.nhash && !st; ++j) {
+        const uint64_t sl = hidx<false>(t, hb, j);
+        st = vec_claim_slot<W>(t.slots + sl, ph, hb, v, keys, n);
+        if (st == 1) loc = sl;
+      }
+      if (!st) {                                 // every candidate taken: the evict kernel
+        s.wkey[begin + e] = kLeftover;
+        s.wmeta[begin + e] = (hb << 33) | i;
+        continue;
+      }
+      const uint32_t res = st == 2 ? 0u : 1u;
+      nnew += res;
+      if (out) out[i] = (uint8_t)res;
+      s.wkey[begin + e] = loc;
+      s.wmeta[begin + e] = (hb << 33) | i;
+      continue;
+    }
     uint64_t b = 0;
     for (uint32_t q = 0; q < steps && !st; ++q) {
       b = vec_bucket(t, hb, q, b);
@@ -459,8 +489,8 @@ __device__ __forceinline__ uint64_t* vec_location(const DevTable& t, uint64_t lo
   return t.overflow + (loc - t.stash_slots);
 }
 
-// Kernel 3 (bucketed): the claimed slots get arena entries, the vectors'
-// words and their final handles.
+// Kernel 3: the claimed slots get arena entries, the vectors' words and
+// their final handles.
 template <int W>
 __global__ __launch_bounds__(kBlock) void vec_commit_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,
                                                              CuckooScratch s) {
@@ -470,7 +500,7 @@ __global__ __launch_bounds__(kBlock) void vec_commit_kernel(DevTable t, const ui
   for (uint32_t e0 = 0; e0 < cnt; e0 += kWave) {
     const uint32_t e = e0 + (uint32_t)lane_id();
     const uint64_t loc = e < cnt ? s.wkey[begin + e] : ~0ull;
-    const bool have = loc != ~0ull;
+    const bool have = loc != ~0ull && loc != kLeftover;
     if (!ballot(have)) continue;
     const uint64_t idx = arena_take(t, have, wave);
     if (!have) continue;

@@ -59,6 +59,8 @@ def parse():
     ap.add_argument("--no-lds", action="store_true", help="skip the LDS occupancy ablation")
     ap.add_argument("--no-vectors", action="store_true", help="skip the state-vector tables")
     ap.add_argument("--no-single-pass", action="store_true", help="skip the single-pass Cuckoo ablation")
+    ap.add_argument("--no-dup-sweep", action="store_true", help="skip the duplication sweep")
+    ap.add_argument("--dup-sweep-only", action="store_true", help="only run the duplication sweep and W1")
     ap.add_argument("--single-pass-only", action="store_true", help="only run the single-pass Cuckoo ablation")
     ap.add_argument("--vectors-only", action="store_true", help="only run the state-vector tables")
     ap.add_argument("--bfs-only", action="store_true",
@@ -94,6 +96,10 @@ def main():
         return
     if args.served_only:
         print(json.dumps({"served": run_served(b, inputs, torch, dev, args.served_requests)}), flush=True)
+        return
+    if args.dup_sweep_only:
+        print(json.dumps({"w1": run_w1(b, inputs, torch, dev, stream),
+                          "duplication_sweep": run_dup_sweep(b, inputs, torch, dev, stream)}), flush=True)
         return
     if args.single_pass_only:
         print(json.dumps({"single_pass": run_single_pass(b, inputs, torch, dev, stream)}), flush=True)
@@ -222,6 +228,11 @@ def main():
     if not args.no_lds:
         lds = run_lds_ablation(b, torch, stream, args, d, keys, out)
 
+    w1 = dup = None
+    if not args.no_dup_sweep:
+        w1 = run_w1(b, inputs, torch, dev, stream)
+        dup = run_dup_sweep(b, inputs, torch, dev, stream)
+
     single = None
     if not args.no_single_pass:
         single = run_single_pass(b, inputs, torch, dev, stream)
@@ -273,6 +284,8 @@ def main():
         "lds_ablation": lds,
         "vectors": vectors,
         "single_pass_ablation": single,
+        "w1": w1,
+        "duplication_sweep": dup,
         "batched": batched,
         "served": served,
         "bfs": bfs,
@@ -404,6 +417,82 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
                             "ok": hits == int(round(h * args.n))})
             t.close()
             log(f"[bench] sweep {kind} lf={lf} done")
+    return res
+
+
+def run_dup_sweep(b, inputs, torch, dev, stream, n=1 << 26, batch=1 << 20, lf=0.8):
+    """The duplication axis of the paper's random-sequence experiment (Sec. 6,
+    Fig. 5, from all-distinct to 1000 occurrences per value; the Cuckoo
+    "bump" of Fig. 6 sits at 450-700): n keys with n/occ distinct values
+    (each at least once, the rest uniform repeats, shuffled), find-or-put in
+    batches into tables sized at 1.25 x distinct (LF 0.8), both designs."""
+    res = []
+    out = torch.empty(n, dtype=torch.uint8, device=dev)
+    for occ in (1, 2, 5, 10, 50, 100, 300, 500, 700, 1000):
+        d = max(1, n // occ)
+        seq = inputs.random_sequence(n, d, seed=inputs.SEED_BASE + 11)
+        keys = torch.from_numpy(seq.view(np.int64)).to(dev)
+        del seq
+        row = {"occurrences_per_key": occ, "keys": n, "distinct": d}
+        for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+            t = b.Table(kind, capacity=max(64, int(np.ceil(d / lf))), nhash=3, max_batch=batch, **kw)
+            ms = None
+            for _ in range(2):                           # warm-up fill, then the timed one
+                t.clear()
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for s0 in range(0, n, batch):
+                    t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
+                e1.record(stream)
+                torch.cuda.synchronize()
+                ms = e0.elapsed_time(e1)
+            row[kind] = {"mops": round(n / ms / 1e3, 1), "ms": round(ms, 3),
+                         "ok": t.size() == d and t.sync_status() == b.HT_OK}
+            t.close()
+        res.append(row)
+        log(f"[bench] duplication {occ}: bucketed {row['bucketed']['mops']} Mops/s, cuckoo {row['cuckoo']['mops']} Mops/s")
+        del keys
+    del out
+    torch.cuda.empty_cache()
+    return res
+
+
+def run_w1(b, inputs, torch, dev, stream):
+    """The small case: 2^20 distinct keys into tables of 2^21 slots (LF 0.5,
+    16 MiB, resident in the last-level cache), then 2^20 queries half present."""
+    ins, q = inputs.small_workload()
+    k = torch.from_numpy(ins.view(np.int64)).to(dev)
+    qk = torch.from_numpy(q.view(np.int64)).to(dev)
+    out = torch.empty(ins.size, dtype=torch.uint8, device=dev)
+    res = {"keys": int(ins.size), "slots": 2 * int(ins.size), "cache_resident": True, "designs": {}}
+    for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+        t = b.Table(kind, capacity=2 * ins.size, nhash=3, **kw)
+        fop = []
+        for _ in range(5):
+            t.clear()
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t.find_or_put(k, out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            fop.append(e0.elapsed_time(e1))
+        ok = t.size() == ins.size
+        qt = []
+        for _ in range(5):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            t.query(qk, out)
+            e1.record(stream)
+            torch.cuda.synchronize()
+            qt.append(e0.elapsed_time(e1))
+        ok = ok and int(out.sum(dtype=torch.int64).item()) == q.size // 2
+        res["designs"][kind] = {"fop_mops": round(ins.size / min(fop[1:]) / 1e3, 1),
+                                "query_mops": round(q.size / min(qt[1:]) / 1e3, 1), "ok": bool(ok)}
+        t.close()
+    log(f"[bench] W1: {res['designs']}")
     return res
 
 

@@ -434,7 +434,10 @@ def run_dup_sweep(b, inputs, torch, dev, stream, n=1 << 26, batch=1 << 20, lf=0.
         keys = torch.from_numpy(seq.view(np.int64)).to(dev)
         del seq
         row = {"occurrences_per_key": occ, "keys": n, "distinct": d}
-        for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+        for name, kind, kw in (("bucketed", "bucketed", dict(bucket_slots=8)),
+                               ("bucketed_one_lane", "bucketed",
+                                dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+                               ("cuckoo", "cuckoo", {})):
             t = b.Table(kind, capacity=max(64, int(np.ceil(d / lf))), nhash=3, max_batch=batch, **kw)
             ms = None
             for _ in range(2):                           # warm-up fill, then the timed one
@@ -447,11 +450,12 @@ def run_dup_sweep(b, inputs, torch, dev, stream, n=1 << 26, batch=1 << 20, lf=0.
                 e1.record(stream)
                 torch.cuda.synchronize()
                 ms = e0.elapsed_time(e1)
-            row[kind] = {"mops": round(n / ms / 1e3, 1), "ms": round(ms, 3),
+            row[name] = {"mops": round(n / ms / 1e3, 1), "ms": round(ms, 3),
                          "ok": t.size() == d and t.sync_status() == b.HT_OK}
             t.close()
         res.append(row)
-        log(f"[bench] duplication {occ}: bucketed {row['bucketed']['mops']} Mops/s, cuckoo {row['cuckoo']['mops']} Mops/s")
+        log(f"[bench] duplication {occ}: bucketed {row['bucketed']['mops']}, one lane "
+            f"{row['bucketed_one_lane']['mops']}, cuckoo {row['cuckoo']['mops']} Mops/s")
         del keys
     del out
     torch.cuda.empty_cache()
@@ -466,7 +470,9 @@ def run_w1(b, inputs, torch, dev, stream):
     qk = torch.from_numpy(q.view(np.int64)).to(dev)
     out = torch.empty(ins.size, dtype=torch.uint8, device=dev)
     res = {"keys": int(ins.size), "slots": 2 * int(ins.size), "cache_resident": True, "designs": {}}
-    for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+    for name, kind, kw in (("bucketed", "bucketed", dict(bucket_slots=8)),
+                           ("bucketed_one_lane", "bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+                           ("cuckoo", "cuckoo", {})):
         t = b.Table(kind, capacity=2 * ins.size, nhash=3, **kw)
         fop = []
         for _ in range(5):
@@ -489,7 +495,7 @@ def run_w1(b, inputs, torch, dev, stream):
             torch.cuda.synchronize()
             qt.append(e0.elapsed_time(e1))
         ok = ok and int(out.sum(dtype=torch.int64).item()) == q.size // 2
-        res["designs"][kind] = {"fop_mops": round(ins.size / min(fop[1:]) / 1e3, 1),
+        res["designs"][name] = {"fop_mops": round(ins.size / min(fop[1:]) / 1e3, 1),
                                 "query_mops": round(q.size / min(qt[1:]) / 1e3, 1), "ok": bool(ok)}
         t.close()
     log(f"[bench] W1: {res['designs']}")
@@ -843,19 +849,23 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
     the timed find-or-put calls."""
     final_states = 121210369          # states reached after level 6 (seed 1)
     res = {"levels": levels, "load_factor": lf, "designs": {}}
-    for kind, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", {})):
+    for kind_name, kind, kw in (("bucketed", "bucketed", dict(bucket_slots=8)),
+                                ("bucketed_one_lane", "bucketed",
+                                 dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+                                ("cuckoo", "cuckoo", {})):
         with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=3, **kw) as t:
             r = t.bfs_explore(inputs.BfsModel(1), levels)
             keys = sum(r["batch_sizes"])
             ms = sum(r["fop_ms"])
-            res["designs"][kind] = {
+            res["designs"][kind_name] = {
                 "batch_sizes": r["batch_sizes"], "new_counts": r["new_counts"],
                 "states": 1 + sum(r["new_counts"]),
                 "fop_ms": [round(x, 3) for x in r["fop_ms"]],
                 "fop_mops_per_level": [round(n / max(x, 1e-9) / 1e3, 1) for n, x in zip(r["batch_sizes"], r["fop_ms"])],
                 "fop_mops": round(keys / ms / 1e3, 1),
                 "occurrences_per_state": round(keys / max(1, sum(r["new_counts"])), 2)}
-        log(f"[bench] bfs {kind}: {res['designs'][kind]['fop_mops']} Mops/s, states {res['designs'][kind]['states']}")
+        log(f"[bench] bfs {kind_name}: {res['designs'][kind_name]['fop_mops']} Mops/s, "
+            f"states {res['designs'][kind_name]['states']}")
     return res
 
 

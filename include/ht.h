@@ -94,7 +94,14 @@ enum {
    * batch can then be stored twice and reported new more than once (a lookup
    * misses a copy that another thread holds in flight); exact only for
    * batches without repeated keys.  Not combinable with key_words > 1. */
-  HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4
+  HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4,
+  /* Bucketed, single-word keys: probe with one lane per key (each lane reads
+   * its buckets eight slots at a time and compare-and-swaps the first empty
+   * slot) instead of a group of B/2 lanes sharing each bucket (Sec. 4.2).
+   * Same table, probe sequence and results; a wave serves 64 keys per turn
+   * instead of 128/B.  Faster where hits dominate and the table is cache
+   * resident; the many-table launch keeps lane groups. */
+  HT_FLAG_BUCKETED_ONE_LANE = 1u << 5
 };
 
 typedef struct {

@@ -34,6 +34,7 @@ HT_FLAG_CACHED_LOADS = 1 << 1
 HT_FLAG_SCRIPTED_HASH = 1 << 2
 HT_FLAG_BUCKETED_PAPER_FULL = 1 << 3
 HT_FLAG_CUCKOO_SINGLE_PASS = 1 << 4
+HT_FLAG_BUCKETED_ONE_LANE = 1 << 5
 
 EMPTY = (1 << 64) - 1
 

@@ -61,4 +61,23 @@ hipError_t bucketed_query(const DevTable& t, const uint64_t* keys, uint64_t n, u
 #undef HT_QRY
 }
 
+// One lane per key (HT_FLAG_BUCKETED_ONE_LANE).
+hipError_t bucketed_lane_find_or_put(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
+                                     uint32_t grid, bool scripted, hipStream_t s) {
+  if (scripted)
+    hipLaunchKernelGGL((bucketed_lane_fop_kernel<true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+  else
+    hipLaunchKernelGGL((bucketed_lane_fop_kernel<false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+  return hipGetLastError();
+}
+
+hipError_t bucketed_lane_query(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
+                               bool scripted, hipStream_t s) {
+  if (scripted)
+    hipLaunchKernelGGL((bucketed_lane_query_kernel<true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+  else
+    hipLaunchKernelGGL((bucketed_lane_query_kernel<false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+  return hipGetLastError();
+}
+
 }  // namespace ht

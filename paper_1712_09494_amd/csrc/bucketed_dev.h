@@ -315,4 +315,82 @@ __global__ __launch_bounds__(kBlock) void bucketed_query_kernel(DevTable t, cons
   }
 }
 
+// ---- one lane per key (HT_FLAG_BUCKETED_ONE_LANE) ---------------------------
+// The same table and probe sequence, but each lane probes whole buckets for
+// its own key: eight slots per step (four independent 16-byte loads), then
+// the first empty slot is compare-and-swapped.  Copies of a key read the same
+// slots in the same order, so they meet at one slot exactly as with a lane
+// group.  A wave serves 64 keys per turn instead of 128/B: less work issued
+// per key, which pays where hits dominate and the table sits in cache.
+
+template <bool SCRIPTED>
+__device__ __forceinline__ uint32_t lane_find_or_put(const DevTable& t, uint64_t k) {
+  if (k == kEmpty) return sentinel_put(t);
+  const uint32_t B = t.bucket_slots;
+  const uint32_t nseq = t.nhash + t.walk;
+  uint64_t b = 0;
+  for (uint32_t j = 0; j < nseq; ++j) {
+    b = probe_bucket<SCRIPTED>(t, k, j, b);
+    uint64_t* bk = t.slots + b * B;
+    for (uint32_t c0 = 0; c0 < B; c0 += 8) {
+      uint64_t x[8];
+      load8(bk + c0, x);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        uint64_t v = x[q];
+        if (v == kEmpty) v = cas64(bk + c0 + q, kEmpty, k);
+        if (v == kEmpty) return 1;     // placed
+        if (v == k) return 0;          // present (or another copy won this slot)
+      }
+    }
+  }
+  return stash_put(t, k);              // every bucket of the sequence full
+}
+
+template <bool SCRIPTED>
+__device__ __forceinline__ uint32_t lane_query(const DevTable& t, uint64_t k, uint32_t sc, uint32_t oc) {
+  if (k == kEmpty) return t.ctr->sentinel ? 1u : 0u;
+  const uint32_t B = t.bucket_slots;
+  const uint32_t nseq = t.nhash + t.walk;
+  uint64_t b = 0;
+  for (uint32_t j = 0; j < nseq; ++j) {
+    b = probe_bucket<SCRIPTED>(t, k, j, b);
+    const uint64_t* bk = t.slots + b * B;
+    for (uint32_t c0 = 0; c0 < B; c0 += 8) {
+      uint64_t x[8];
+      load8(bk + c0, x);
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (x[q] == k) return 1;
+        if (x[q] == kEmpty) return 0;  // slots fill as a prefix and a full sequence precedes the stash
+      }
+    }
+  }
+  return (sc | oc) && stash_query(t, k, sc, oc) ? 1u : 0u;
+}
+
+template <bool SCRIPTED>
+__global__ __launch_bounds__(kBlock) void bucketed_lane_fop_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                                    uint64_t n, uint8_t* __restrict__ out) {
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  unsigned long long nnew = 0;
+  for (uint64_t i = first; i < n; i += stride) {
+    const uint32_t res = lane_find_or_put<SCRIPTED>(t, keys[i]);
+    if (out) out[i] = (uint8_t)res;
+    nnew += res == 1;
+  }
+  wave_count(t.ctr->size, nnew, (uint32_t)(first / kWave));
+}
+
+template <bool SCRIPTED>
+__global__ __launch_bounds__(kBlock) void bucketed_lane_query_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                                      uint64_t n, uint8_t* __restrict__ out) {
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride)
+    out[i] = (uint8_t)lane_query<SCRIPTED>(t, keys[i], sc, oc);
+}
+
 }  // namespace ht

@@ -187,6 +187,17 @@ __device__ __forceinline__ void load_pair(const uint64_t* p, uint64_t& a, uint64
   }
 }
 
+// Eight consecutive slots (64-byte aligned: bucket widths are multiples of
+// 8 slots), four independent 16-byte loads in flight together.
+__device__ __forceinline__ void load8(const uint64_t* p, uint64_t (&x)[8]) {
+#pragma unroll
+  for (int k = 0; k < 8; k += 2) {
+    const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(p + k);
+    x[k] = y.x;
+    x[k + 1] = y.y;
+  }
+}
+
 // ---- stash and overflow list ---------------------------------------------
 // The stash (Sec. 4.1, after Alcantara et al.) holds keys that could not be
 // placed; it is open-addressed with linear probing so that a lookup costs one

@@ -19,6 +19,9 @@ hipError_t bucketed_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint
 hipError_t bucketed_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
                           hipStream_t);
 uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R);
+hipError_t bucketed_lane_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool,
+                                     hipStream_t);
+hipError_t bucketed_lane_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
 hipError_t cuckoo_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
                         hipStream_t);
 hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
@@ -271,8 +274,11 @@ int validate_config(const ht_config* c) {
   if (c->keys_per_group != 0 && c->keys_per_group != 1 && c->keys_per_group != 2 && c->keys_per_group != 4)
     return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
-                             HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS))
+                             HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS |
+                             HT_FLAG_BUCKETED_ONE_LANE))
     return fail(HT_EINVAL, "unknown flag bits");
+  if ((c->flags & HT_FLAG_BUCKETED_ONE_LANE) && (c->kind != HT_BUCKETED || c->key_words > 1))
+    return fail(HT_EINVAL, "the one-lane flag is for bucketed tables of single-word keys");
   if ((c->flags & HT_FLAG_CUCKOO_SINGLE_PASS) && (c->kind != HT_CUCKOO || c->key_words > 1))
     return fail(HT_EINVAL, "the single-pass flag is for Cuckoo tables of single-word keys");
   if (c->key_words != 0 && c->key_words != 1 && c->key_words != 2 && c->key_words != 4)
@@ -425,6 +431,12 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
+  if (t->cfg.kind == HT_BUCKETED && (t->cfg.flags & HT_FLAG_BUCKETED_ONE_LANE)) {
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    KernelTimer kt("bucketed_lane_fop", s);
+    HT_HIP(bucketed_lane_find_or_put(d, keys, n, out, (uint32_t)blocks, scripted, s));
+    return HT_OK;
+  }
   if (t->cfg.kind == HT_BUCKETED) {
     const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R);
     const uint64_t waves = (n + g - 1) / g;
@@ -473,6 +485,12 @@ int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStr
   }
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
+  if (t->cfg.kind == HT_BUCKETED && (t->cfg.flags & HT_FLAG_BUCKETED_ONE_LANE)) {
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    KernelTimer kt("bucketed_lane_query", s);
+    HT_HIP(bucketed_lane_query(d, keys, n, out, (uint32_t)blocks, scripted, s));
+    return HT_OK;
+  }
   if (t->cfg.kind == HT_BUCKETED) {
     // a query issues no atomics, so a second key in flight per group pays off
     // even where find-or-put prefers one (measured: +11-14% at B = 8 and 16)

@@ -97,17 +97,6 @@ __device__ __forceinline__ uint64_t vec_bucket(const DevTable& t, uint64_t hb, u
   return prev + 1 == t.nrange ? 0 : prev + 1;
 }
 
-// Eight consecutive slots (64-byte aligned: bucket widths are multiples of
-// 8 slots), four independent 16-byte loads in flight together.
-__device__ __forceinline__ void load8(const uint64_t* p, uint64_t (&x)[8]) {
-#pragma unroll
-  for (int k = 0; k < 8; k += 2) {
-    const ulonglong2 y = *reinterpret_cast<const ulonglong2*>(p + k);
-    x[k] = y.x;
-    x[k + 1] = y.y;
-  }
-}
-
 template <int W>
 __device__ bool vec_lookup_bucketed(const DevTable& t, uint64_t hb, const uint64_t (&v)[W]) {
   const uint32_t B = t.bucket_slots;

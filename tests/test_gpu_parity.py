@@ -30,10 +30,12 @@ DESIGNS = {
     "cuckoo_r4": dict(kind="cuckoo", keys_per_group=4),
     "bkt16_paperfull": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL),
     "bkt8_lds64k": dict(kind="bucketed", bucket_slots=8, lds_bytes=65536),
+    "bkt8_lane": dict(kind="bucketed", bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
+    "bkt64_lane": dict(kind="bucketed", bucket_slots=64, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
     "cuckoo_lds64k": dict(kind="cuckoo", lds_bytes=65536),
 }
 MAIN = ["bkt16", "bkt8", "bkt16_cached", "cuckoo", "cuckoo_paper"]
-MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4"]
+MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4", "bkt8_lane"]
 
 
 def dev(a):

@@ -34,11 +34,13 @@ def positions(r):
 
 @pytest.mark.parametrize("B", [8, 16, 32, 64])
 @pytest.mark.parametrize("lf", [0.5, 0.9])
-def test_bucketed_prefix_and_spill_order(B, lf):
+@pytest.mark.parametrize("flags", [0, b.HT_FLAG_BUCKETED_ONE_LANE])
+def test_bucketed_prefix_and_spill_order(B, lf, flags):
     """Occupied slots of each bucket form a prefix; a key found in h_j's bucket
-    has the buckets of h_1..h_{j-1} full (Sec. 4.2 probe order)."""
+    has the buckets of h_1..h_{j-1} full (Sec. 4.2 probe order); with lane
+    groups and with one lane per key."""
     n = 20000
-    t = b.Table("bucketed", capacity=int(n / lf), nhash=3, bucket_slots=B)
+    t = b.Table("bucketed", capacity=int(n / lf), nhash=3, bucket_slots=B, flags=flags)
     keys = inputs.uniform_keys(n, seed=B)
     t.find_or_put(dev(keys))
     st = t.stats()

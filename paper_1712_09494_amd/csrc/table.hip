@@ -227,14 +227,16 @@ int free_scratch(ht_table* t) {
   return HT_OK;
 }
 
-// Cuckoo scratch for batches up to n keys (one allocation).
+// Find-or-put scratch (Cuckoo and vector tables) for batches up to n keys (one allocation).
 int reserve_scratch(ht_table* t, uint64_t n) {
   if (t->cfg.kind != HT_CUCKOO && t->cfg.key_words <= 1) return HT_OK;
   if (n <= t->scratch_n && t->dset) return HT_OK;
   if (n < 1024) n = 1024;
   HT_HIP(hipDeviceSynchronize());
   free_scratch(t);
-  const uint64_t ds = pow2_at_least(2 * n);
+  // the deduplication set serves Cuckoo tables only (bucketed vector tables
+  // deduplicate in their slots); keep a token one otherwise
+  const uint64_t ds = t->cfg.kind == HT_CUCKOO ? pow2_at_least(2 * n) : 64;
   const uint64_t nw = (uint64_t)max_blocks(t) * (kBlock / kWave);
   const size_t b_dset = align_up(ds * 8, 256);
   const size_t b_k = align_up(n * 8, 256);
@@ -243,7 +245,7 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c);
   if (e != hipSuccess) {
     (void)hipGetLastError();
-    return fail(HT_ENOMEM, std::string("hipMalloc of cuckoo scratch failed: ") + hipGetErrorString(e));
+    return fail(HT_ENOMEM, std::string("hipMalloc of find-or-put scratch failed: ") + hipGetErrorString(e));
   }
   char* c = static_cast<char*>(p);
   t->dset = reinterpret_cast<uint64_t*>(c);

@@ -93,7 +93,9 @@ enum {
    * Sec. 5.1.1 (a thread that evicts its own key stops).  Keys repeated in a
    * batch can then be stored twice and reported new more than once (a lookup
    * misses a copy that another thread holds in flight); exact only for
-   * batches without repeated keys.  Not combinable with key_words > 1. */
+   * batches without repeated keys.  Not combinable with key_words > 1.  The
+   * many-table call and the serving engine always use the exact three-kernel
+   * insertion. */
   HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4,
   /* Bucketed, single-word keys: probe with one lane per key (each lane reads
    * its buckets eight slots at a time and compare-and-swaps the first empty

@@ -770,7 +770,9 @@ def batched_workload(inputs, ntables=256, lf=0.6):
 
 def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
     """Many tables: 256 plain per-table calls vs one persistent launch (plan)
-    vs the plan's launch replayed from a captured HIP graph."""
+    vs the plan's launch replayed from a captured HIP graph; then queries of
+    every batch, 256 per-table calls vs one many-table query call (both by
+    host wall clock, Python included)."""
     from paper_1712_09494_amd import tune
     t0 = time.time()
     caps, keys, distinct = batched_workload(inputs, ntables, lf)
@@ -827,13 +829,36 @@ def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
         torch.cuda.synchronize()
         graph_ms = timed(lambda: g.replay())
         ok_graph = plan.status() == b.HT_OK and all(t.size() == d for t, d in zip(tables, distinct))
+        # queries of every table's batch (all members): one call per table vs
+        # one many-table query call (descriptor build, copy and sync included)
+        qouts = [torch.empty(k.numel(), dtype=torch.uint8, device=dev) for k in kd]
+
+        def timed_q(fn):
+            best = None
+            for _ in range(reps):
+                torch.cuda.synchronize()
+                t0q = time.perf_counter()
+                fn()
+                torch.cuda.synchronize()
+                ms = (time.perf_counter() - t0q) * 1e3
+                best = ms if best is None else min(best, ms)
+            return best
+
+        q_plain_ms = timed_q(lambda: [t.query(k, o) for t, k, o in zip(tables, kd, qouts)])
+        ok_q = all(bool(o.all()) for o in qouts)
+        for o in qouts:
+            o.zero_()
+        q_multi_ms = timed_q(lambda: b.query_multi(tables, kd, qouts))
+        ok_q = ok_q and all(bool(o.all()) for o in qouts)
         res["designs"][kind] = {
+            "query_plain_ms": round(q_plain_ms, 3), "query_multi_ms": round(q_multi_ms, 3),
             "plain_ms": round(plain_ms, 3), "plan_ms": round(plan_ms, 3), "graph_ms": round(graph_ms, 3),
             "plain_mops": round(total / plain_ms / 1e3, 1), "graph_mops": round(total / graph_ms / 1e3, 1),
             "speedup_graph_vs_plain": round(plain_ms / graph_ms, 2),
             "tuned_classes": {k: v for k, v in sorted(tuned.items())},
-            "ok": bool(ok_plain and ok_plan and ok_graph)}
-        log(f"[bench] batched {kind}: plain {plain_ms:.2f} ms, plan {plan_ms:.2f} ms, graph {graph_ms:.2f} ms")
+            "ok": bool(ok_plain and ok_plan and ok_graph and ok_q)}
+        log(f"[bench] batched {kind}: plain {plain_ms:.2f} ms, plan {plan_ms:.2f} ms, graph {graph_ms:.2f} ms; "
+            f"queries plain {q_plain_ms:.2f} ms, many-table {q_multi_ms:.2f} ms")
         del g
         plan.close()
         for t in tables:
@@ -916,9 +941,10 @@ def run_served(b, inputs, torch, dev, nreq=1024, ntables=64, slots_log2=24):
                     "peak_staging_MB": round(st["peak_staging"] / 2 ** 20, 1)}
 
         zeros = [0.0] * nreq
-        seq0 = run(zeros, sequential=True)
+        # a backlog replay lasts tens of ms and is bound by the host loop: best of 5
+        seq0 = run(zeros, reps=5, sequential=True)
         sat = seq0["requests_per_s"]
-        d = {"saturation_requests_per_s": sat, "sequential_backlog": seq0, "served_backlog": run(zeros),
+        d = {"saturation_requests_per_s": sat, "sequential_backlog": seq0, "served_backlog": run(zeros, reps=5),
              "poisson": []}
         log(f"[bench] served {design} backlog: sequential {seq0['requests_per_s']} req/s, "
             f"served {d['served_backlog']['requests_per_s']} req/s")

@@ -204,6 +204,19 @@ int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
                          uint32_t ntables, hipStream_t stream);
 
+/* Query `ntables` tables at once (the lookups of Sec. 4.1 and 4.2, applied
+ * to many tables): d_out_found[i][j] = 1 if d_keys[i][j] is a member of
+ * t[i], else 0.  Arguments as for ht_find_or_put_multi (host arrays of
+ * device pointers); flag pointers must not be NULL where n[i] > 0.  Tables
+ * may mix kinds and repeat; scripted-hash and vector tables are rejected.
+ * Batches too small to fill the device alone share one kernel (bucketed
+ * tables read by lane groups, Cuckoo tables by one lane per key); a batch
+ * that fills it alone runs the single-table query.  Results equal one
+ * ht_query per table.  Allocates the descriptors and synchronises `stream`. */
+int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys,
+                   const uint64_t* n, uint8_t* const* d_out_found,
+                   uint32_t ntables, hipStream_t stream);
+
 typedef struct ht_multi_plan ht_multi_plan;
 
 /* Prepare a many-table find-or-put: validates the arguments, reserves each
@@ -348,7 +361,7 @@ typedef struct {
   uint64_t peak_staging;    /* largest staging in use at once, bytes */
   uint64_t staging_bytes;   /* the budget */
   uint32_t groups;          /* launch groups issued */
-  uint32_t merged_launches; /* many-table launches among them */
+  uint32_t merged_launches; /* groups that used many-table launches */
   uint32_t max_inflight_groups;
   uint32_t throttled;       /* admissions deferred for lack of staging */
 } ht_server_stats;

@@ -185,6 +185,7 @@ _PROTOS = {
     "ht_insert": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_query": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_find_or_put_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
+    "ht_query_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
     "ht_multi_plan_create": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32,
                                        C.POINTER(_vp)]),
     "ht_multi_plan_launch": (C.c_int, [_vp, _vp]),
@@ -365,6 +366,20 @@ def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=No
     nn = (_u64 * n)(*[k.numel() for k in ks])
     op = (_vp * n)(*[o.data_ptr() for o in os_])
     _check(load().ht_find_or_put_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_find_or_put_multi")
+    return os_
+
+
+def ht_query_multi(handles: Sequence[int], keys_list, outs=None, stream=None):
+    n = len(handles)
+    ks = [_key_tensor(k) for k in keys_list]
+    if len(ks) != n:
+        raise ValueError("one key tensor per table")
+    os_ = [_out_tensor(None if outs is None else outs[i], ks[i].numel(), ks[i]) for i in range(n)]
+    th = (_vp * n)(*handles)
+    kp = (_vp * n)(*[k.data_ptr() for k in ks])
+    nn = (_u64 * n)(*[k.numel() for k in ks])
+    op = (_vp * n)(*[o.data_ptr() for o in os_])
+    _check(load().ht_query_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_query_multi")
     return os_
 
 
@@ -667,6 +682,10 @@ class Server:
 
 def find_or_put_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):
     return ht_find_or_put_multi([t.handle for t in tables], keys_list, outs, stream)
+
+
+def query_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):
+    return ht_query_multi([t.handle for t in tables], keys_list, outs, stream)
 
 
 def u64(t) -> np.ndarray:

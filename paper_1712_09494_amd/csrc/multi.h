@@ -33,22 +33,25 @@ struct MultiCuckooSpec {
   bool paper;
 };
 
+// One table of a many-table query (either kind).
+struct MultiQuerySpec {
+  DevTable t;
+  const uint64_t* keys;
+  uint8_t* out;
+  uint64_t n;
+  bool cuckoo;
+};
+
 // Per-stream-slot descriptor buffers for launches whose table set changes
 // every time (pinned host staging + device copy; nothing allocated per launch).
 struct MultiCuckoo;
+struct MultiQuery;
 
 struct MultiDyn {
-  MultiTable* d_tabs = nullptr;
-  uint64_t* d_items = nullptr;
-  MultiTable* h_tabs = nullptr;
-  uint64_t* h_items = nullptr;
-  MultiCuckoo* d_ctabs = nullptr;
-  uint64_t* d_citems = nullptr;
-  MultiCuckoo* h_ctabs = nullptr;
-  uint64_t* h_citems = nullptr;
   void* d_base = nullptr;
   void* h_base = nullptr;
-  uint32_t cap_tabs = 0, cap_items = 0;   // per kind
+  uint32_t cap_tabs = 0;     // tables per kind
+  uint32_t cap_items = 0;    // find-or-put items per kind
 };
 
 // A prepared many-table launch: descriptors and item lists in one device
@@ -72,9 +75,19 @@ hipError_t multi_cuckoo_launch(const MultiPlanDev& plan, int phase, hipStream_t 
 hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items);
 void multi_dyn_free(MultiDyn& d);
 uint64_t multi_items_for(uint64_t n);
-// Bucketed tables in one persistent launch, then the three Cuckoo phase
-// launches over the Cuckoo tables; all on stream s.
-hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
-                            uint32_t nc, uint32_t max_blocks, hipStream_t s);
+// One launch group on stream s: one copy of every descriptor, then the
+// bucketed find-or-puts in one persistent launch, the three Cuckoo phase
+// launches, and the queries of every table (either kind) in one launch.
+hipError_t multi_dyn_issue(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
+                           uint32_t nc, const MultiQuerySpec* qs, uint32_t nq, uint32_t max_blocks, hipStream_t s);
+// True when a query batch alone gives every wave slot of a max_blocks grid
+// a turn: such a batch is better served by the single-table query, which
+// keeps its table's probes together in cache (measured on 256 tables of
+// 2^6..2^26 slots: merged large batches ran 10-20% slower than one launch
+// per table), while smaller batches gain from sharing one launch.
+bool multi_query_alone(const MultiQuerySpec& q, uint32_t max_blocks);
+// Queries of nq tables in one launch, allocating the descriptors and
+// synchronising s (one-off calls).
+hipError_t multi_query_once(const MultiQuerySpec* qs, uint32_t nq, uint32_t max_blocks, hipStream_t s);
 
 }  // namespace ht

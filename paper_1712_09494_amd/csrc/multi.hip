@@ -122,6 +122,85 @@ __global__ __launch_bounds__(kBlock) void multi_cuckoo_scrub_kernel(const MultiC
   }
 }
 
+// Queries of many tables, of either kind, in one launch.  A query writes
+// nothing to the table, so no phases are needed.  The launch is a list of
+// items, each a run of one table's keys; table i owns items first_i ..
+// first_{i+1} - 1, and wave w takes items w, w + W, w + 2W, ...  A wave's
+// item index only grows, so it finds each item's table by walking the
+// descriptors forward (no item list is stored).  Items are short, so the
+// waves sweep the tables in order, a few at a time, and the tables being
+// probed stay in cache together, as when each table has a launch of its own.
+// A bucketed table is read as by the single-table query: groups of B/2 lanes
+// read a whole bucket in one access, two keys per group in flight, and stop
+// at the key or at the first bucket with an empty slot; a Cuckoo table gives
+// each lane a key and reads h_1, h_2, ..., stopping at the key or (distinct
+// indices) an empty slot.  Both then check the stash and overflow list if
+// those hold keys.
+struct MultiQuery {
+  DevTable t;
+  const uint64_t* keys;
+  uint8_t* out;
+  uint64_t n;
+  uint64_t chunk;           // keys per item
+  uint64_t first;           // index of the table's first item
+  uint32_t cuckoo;
+  uint32_t pad_;
+};
+
+__global__ __launch_bounds__(kBlock) void multi_query_kernel(const MultiQuery* __restrict__ tabs, uint32_t ntabs,
+                                                             uint64_t nitems) {
+  const int lane = lane_id();
+  const uint64_t wave =
+      __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  uint32_t ti = 0;
+  for (uint64_t idx = wave; idx < nitems; idx += nwaves) {
+    while (ti + 1 < ntabs && idx >= tabs[ti + 1].first) ++ti;
+    const MultiQuery& m = tabs[ti];
+    const uint64_t begin = (idx - m.first) * m.chunk;
+    const uint64_t end = begin + m.chunk < m.n ? begin + m.chunk : m.n;
+    const uint32_t sc = m.t.ctr->stash_count;
+    const uint32_t oc = m.t.ctr->overflow_count;
+    if (m.cuckoo) {
+      for (uint64_t base = begin; base < end; base += kWave) {
+        const uint64_t i = base + lane;
+        const uint64_t k[1] = {i < end ? m.keys[i] : kEmpty};
+        const bool live[1] = {i < end && k[0] != kEmpty};
+        bool hit[1];
+        cuckoo_lookup<1, false>(m.t, k, live, hit);
+        if (i < end) {
+          bool h = hit[0];
+          if (k[0] == kEmpty) h = m.t.ctr->sentinel != 0;
+          else if (!h && (sc | oc)) h = stash_query(m.t, k[0], sc, oc);
+          m.out[i] = h ? 1 : 0;
+        }
+      }
+    } else {
+      const uint32_t L = m.t.bucket_slots / 2;
+      const uint32_t G = kWave / L;
+      const int grp = lane / (int)L;
+      const int gl = lane & (int)(L - 1);
+      for (uint64_t base = begin; base < end; base += 2 * G) {
+        uint64_t k[2];
+        bool act[2];
+        uint32_t res[2];
+#pragma unroll
+        for (int r = 0; r < 2; ++r) {
+          const uint64_t i = base + (uint64_t)r * G + grp;
+          act[r] = i < end;
+          k[r] = act[r] ? m.keys[i] : 0;
+        }
+        bucket_query<0, 2, false>(m.t, k, act, sc, oc, res);
+        if (gl == 0) {
+#pragma unroll
+          for (int r = 0; r < 2; ++r)
+            if (act[r]) m.out[base + (uint64_t)r * G + grp] = (uint8_t)res[r];
+        }
+      }
+    }
+  }
+}
+
 // Item size for a launch of `total` keys on a device with `max_waves` wave
 // slots: a power of two in [64, 4096] giving about max_waves items (small
 // launches still fill every wave slot).
@@ -137,6 +216,32 @@ uint32_t multi_grid(uint64_t nitems, uint32_t max_blocks) {
 }
 
 // ---- host side ------------------------------------------------------------
+
+static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+
+// Fill the descriptors and (table, region) items of `nt` bucketed tables
+// (find-or-put).  Returns the item count, or ~0 when the items would exceed
+// cap_items.
+static uint64_t fill_bucketed(const MultiSpec* sp, uint32_t nt, uint64_t max_waves, MultiTable* tabs,
+                              uint64_t* items, uint64_t cap_items) {
+  uint64_t total = 0;
+  for (uint32_t i = 0; i < nt; ++i) total += sp[i].n;
+  const uint64_t chunk = multi_chunk(total, max_waves);
+  uint64_t nitems = 0;
+  for (uint32_t i = 0; i < nt; ++i) {
+    MultiTable& m = tabs[i];
+    std::memset(&m, 0, sizeof(m));
+    m.t = sp[i].t;
+    m.keys = sp[i].keys;
+    m.out = sp[i].out;
+    m.n = sp[i].n;
+    m.chunk = chunk;
+    m.nregions = (uint32_t)((sp[i].n + chunk - 1) / chunk);
+    if (nitems + m.nregions > cap_items) return ~0ull;
+    for (uint64_t r = 0; r < m.nregions; ++r) items[nitems++] = make_item(i, r);
+  }
+  return nitems;
+}
 
 // Fill the descriptors and (table, region) items of `nc` Cuckoo tables.  A
 // region holds at least a whole item's worth of keys (a multiple of 64) and a
@@ -170,7 +275,55 @@ static uint64_t fill_cuckoo(const MultiCuckooSpec* cs, uint32_t nc, uint64_t max
   return nitems;
 }
 
-static size_t align256(size_t b) { return (b + 255) / 256 * 256; }
+// Keys one wave answers per turn of the many-table query: 64 (a key per
+// lane) for a Cuckoo table, two per lane group of B/2 lanes for a bucketed
+// one.
+static uint64_t query_turn(const MultiQuerySpec& q) {
+  return q.cuckoo ? (uint64_t)kWave : 2ull * (kWave / (q.t.bucket_slots / 2));
+}
+
+bool multi_query_alone(const MultiQuerySpec& q, uint32_t max_blocks) {
+  return q.n >= (uint64_t)max_blocks * (kBlock / kWave) * query_turn(q);
+}
+
+// Fill the descriptors of a many-table query; returns the item count.  An
+// item is the same number of turns for every table: the fewest (a power of
+// two, at most kQueryTurns) that leave at most one item per wave slot, so a
+// small launch answers every key in one turn and a large one has many short
+// items, swept in table order.
+constexpr uint64_t kQueryTurns = 16;
+
+static uint64_t fill_query(const MultiQuerySpec* qs, uint32_t nq, uint64_t max_waves, MultiQuery* tabs) {
+  uint64_t turns = 1;
+  for (; turns < kQueryTurns; turns <<= 1) {
+    uint64_t count = 0;
+    for (uint32_t i = 0; i < nq; ++i) {
+      const uint64_t c = query_turn(qs[i]) * turns;
+      count += (qs[i].n + c - 1) / c;
+    }
+    if (count <= max_waves) break;
+  }
+  uint64_t nitems = 0;
+  for (uint32_t i = 0; i < nq; ++i) {
+    MultiQuery& m = tabs[i];
+    std::memset(&m, 0, sizeof(m));
+    m.t = qs[i].t;
+    m.keys = qs[i].keys;
+    m.out = qs[i].out;
+    m.n = qs[i].n;
+    m.chunk = query_turn(qs[i]) * turns;
+    m.first = nitems;
+    m.cuckoo = qs[i].cuckoo ? 1u : 0u;
+    nitems += (qs[i].n + m.chunk - 1) / m.chunk;
+  }
+  return nitems;
+}
+
+static void launch_query(const MultiQuery* d_tabs, uint32_t nq, uint64_t nitems, uint32_t max_blocks,
+                         hipStream_t s) {
+  hipLaunchKernelGGL(multi_query_kernel, dim3(multi_grid(nitems, max_blocks)), dim3(kBlock), 0, s, d_tabs, nq,
+                     nitems);
+}
 
 // Build descriptors and the item lists on the host and copy them to one
 // device allocation (synchronous).  Returns hipSuccess or the HIP error
@@ -180,30 +333,18 @@ hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, const std::vect
                             uint32_t max_blocks, MultiPlanDev& plan) {
   const uint64_t max_waves = (uint64_t)max_blocks * (kBlock / kWave);
   const uint32_t nt = (uint32_t)specs.size();
-  std::vector<MultiTable> tabs(nt);
-  std::vector<uint64_t> items;
-  uint64_t total = 0;
-  for (const auto& sp : specs) total += sp.n;
-  const uint64_t chunk = multi_chunk(total, max_waves);
-  for (uint32_t i = 0; i < nt; ++i) {
-    const MultiSpec& sp = specs[i];
-    MultiTable& m = tabs[i];
-    std::memset(&m, 0, sizeof(m));
-    m.t = sp.t;
-    m.keys = sp.keys;
-    m.out = sp.out;
-    m.n = sp.n;
-    m.chunk = chunk;
-    m.nregions = sp.n ? (uint32_t)((sp.n + m.chunk - 1) / m.chunk) : 0;
-    for (uint64_t r = 0; r < m.nregions; ++r) items.push_back(make_item(i, r));
-  }
   const uint32_t nc = (uint32_t)cspecs.size();
-  std::vector<MultiCuckoo> ctabs(nc);
-  uint64_t cap_c = 0;
+  uint64_t cap_b = 0, cap_c = 0;
+  for (const auto& sp : specs) cap_b += multi_items_for(sp.n);
   for (const auto& sp : cspecs) cap_c += multi_items_for(sp.n);
+  std::vector<MultiTable> tabs(nt);
+  std::vector<uint64_t> items(cap_b);
+  std::vector<MultiCuckoo> ctabs(nc);
   std::vector<uint64_t> citems(cap_c);
+  const uint64_t nit = fill_bucketed(specs.data(), nt, max_waves, tabs.data(), items.data(), cap_b);
   const uint64_t ncit = fill_cuckoo(cspecs.data(), nc, max_waves, ctabs.data(), citems.data(), cap_c);
-  if (ncit == ~0ull) return hipErrorInvalidValue;
+  if (nit == ~0ull || ncit == ~0ull) return hipErrorInvalidValue;
+  items.resize(nit);
   citems.resize(ncit);
   plan.nitems = (uint32_t)items.size();
   plan.ncitems = (uint32_t)citems.size();
@@ -254,34 +395,24 @@ hipError_t multi_cuckoo_launch(const MultiPlanDev& plan, int phase, hipStream_t 
 }
 
 // ---- per-launch descriptors (serving loop) -----------------------------------
-// A launch whose table set changes every time: descriptors and items are
-// written into pinned host buffers owned by one stream slot and copied to
-// that slot's device buffers on the launch stream, so nothing is allocated
-// per launch.  The caller reuses a slot only after its previous launch has
-// completed.
+// A launch group whose table set changes every time: its descriptors and
+// items are packed one after another into a pinned host buffer owned by one
+// stream slot and copied to that slot's device buffer with ONE copy on the
+// launch stream, so nothing is allocated per group.  The caller reuses a slot
+// only after its previous group has completed.
+
+static size_t dyn_bytes(uint32_t cap_tabs, uint64_t cap_items) {
+  return align256(sizeof(MultiTable) * cap_tabs) + align256(cap_items * 8) +
+         align256(sizeof(MultiCuckoo) * cap_tabs) + align256(cap_items * 8) + align256(sizeof(MultiQuery) * cap_tabs);
+}
 
 hipError_t multi_dyn_alloc(MultiDyn& d, uint32_t cap_tabs, uint32_t cap_items) {
   d.cap_tabs = cap_tabs;
   d.cap_items = cap_items;
-  const size_t b_tabs = align256(sizeof(MultiTable) * cap_tabs);
-  const size_t b_items = align256((size_t)cap_items * 8);
-  const size_t b_ctabs = align256(sizeof(MultiCuckoo) * cap_tabs);
-  const size_t bytes = b_tabs + 2 * b_items + b_ctabs;
+  const size_t bytes = dyn_bytes(cap_tabs, cap_items);
   hipError_t e = hipMalloc(&d.d_base, bytes);
   if (e != hipSuccess) return e;
-  e = hipHostMalloc(&d.h_base, bytes, hipHostMallocDefault);
-  if (e != hipSuccess) return e;
-  char* c = static_cast<char*>(d.d_base);
-  char* h = static_cast<char*>(d.h_base);
-  d.d_tabs = reinterpret_cast<MultiTable*>(c);
-  d.h_tabs = reinterpret_cast<MultiTable*>(h);
-  d.d_items = reinterpret_cast<uint64_t*>(c + b_tabs);
-  d.h_items = reinterpret_cast<uint64_t*>(h + b_tabs);
-  d.d_ctabs = reinterpret_cast<MultiCuckoo*>(c + b_tabs + b_items);
-  d.h_ctabs = reinterpret_cast<MultiCuckoo*>(h + b_tabs + b_items);
-  d.d_citems = reinterpret_cast<uint64_t*>(c + b_tabs + b_items + b_ctabs);
-  d.h_citems = reinterpret_cast<uint64_t*>(h + b_tabs + b_items + b_ctabs);
-  return hipSuccess;
+  return hipHostMalloc(&d.h_base, bytes, hipHostMallocDefault);
 }
 
 void multi_dyn_free(MultiDyn& d) {
@@ -293,49 +424,65 @@ void multi_dyn_free(MultiDyn& d) {
 // Number of work items a table of n keys needs.
 uint64_t multi_items_for(uint64_t n) { return (n + 63) / 64; }
 
-hipError_t multi_dyn_launch(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
-                            uint32_t nc, uint32_t max_blocks, hipStream_t s) {
-  if (nt > d.cap_tabs || nc > d.cap_tabs) return hipErrorInvalidValue;
+hipError_t multi_dyn_issue(MultiDyn& d, const MultiSpec* specs, uint32_t nt, const MultiCuckooSpec* cspecs,
+                           uint32_t nc, const MultiQuerySpec* qs, uint32_t nq, uint32_t max_blocks, hipStream_t s) {
+  if (nt > d.cap_tabs || nc > d.cap_tabs || nq > d.cap_tabs) return hipErrorInvalidValue;
   const uint64_t max_waves = (uint64_t)max_blocks * (kBlock / kWave);
-  uint64_t total = 0;
-  for (uint32_t i = 0; i < nt; ++i) total += specs[i].n;
-  const uint64_t chunk = multi_chunk(total, max_waves);
-  uint32_t nitems = 0;
-  for (uint32_t i = 0; i < nt; ++i) {
-    MultiTable& m = d.h_tabs[i];
-    std::memset(&m, 0, sizeof(m));
-    m.t = specs[i].t;
-    m.keys = specs[i].keys;
-    m.out = specs[i].out;
-    m.n = specs[i].n;
-    m.chunk = chunk;
-    m.nregions = (uint32_t)((specs[i].n + chunk - 1) / chunk);
-    if (nitems + m.nregions > d.cap_items) return hipErrorInvalidValue;
-    for (uint64_t r = 0; r < m.nregions; ++r) d.h_items[nitems++] = make_item(i, r);
-  }
-  const uint64_t ncit = fill_cuckoo(cspecs, nc, max_waves, d.h_ctabs, d.h_citems, d.cap_items);
+  char* h = static_cast<char*>(d.h_base);
+  char* dv = static_cast<char*>(d.d_base);
+  size_t o = 0;
+  auto tabs = reinterpret_cast<MultiTable*>(h + o);
+  const size_t o_tabs = o;
+  o += align256(sizeof(MultiTable) * nt);
+  const size_t o_items = o;
+  const uint64_t nit = fill_bucketed(specs, nt, max_waves, tabs, reinterpret_cast<uint64_t*>(h + o), d.cap_items);
+  if (nit == ~0ull) return hipErrorInvalidValue;
+  o += align256(nit * 8);
+  const size_t o_ctabs = o;
+  o += align256(sizeof(MultiCuckoo) * nc);
+  const size_t o_citems = o;
+  const uint64_t ncit = fill_cuckoo(cspecs, nc, max_waves, reinterpret_cast<MultiCuckoo*>(h + o_ctabs),
+                                    reinterpret_cast<uint64_t*>(h + o), d.cap_items);
   if (ncit == ~0ull) return hipErrorInvalidValue;
-  hipError_t e = hipSuccess;
-  if (nitems) {
-    e = hipMemcpyAsync(d.d_tabs, d.h_tabs, sizeof(MultiTable) * nt, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d.d_items, d.h_items, (size_t)nitems * 8, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(multi_fill_kernel, dim3(multi_grid(nitems, max_blocks)), dim3(kBlock), 0, s, d.d_tabs,
-                       d.d_items, nitems);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
-  }
+  o += align256(ncit * 8);
+  const size_t o_qtabs = o;
+  const uint64_t nqit = fill_query(qs, nq, max_waves, reinterpret_cast<MultiQuery*>(h + o_qtabs));
+  o += align256(sizeof(MultiQuery) * nq);
+  if (!nit && !ncit && !nqit) return hipSuccess;
+  hipError_t e = hipMemcpyAsync(dv, h, o, hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  if (nit)
+    hipLaunchKernelGGL(multi_fill_kernel, dim3(multi_grid(nit, max_blocks)), dim3(kBlock), 0, s,
+                       reinterpret_cast<const MultiTable*>(dv + o_tabs),
+                       reinterpret_cast<const uint64_t*>(dv + o_items), (uint32_t)nit);
   if (ncit) {
-    e = hipMemcpyAsync(d.d_ctabs, d.h_ctabs, sizeof(MultiCuckoo) * nc, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(d.d_citems, d.h_citems, (size_t)ncit * 8, hipMemcpyHostToDevice, s);
-    if (e != hipSuccess) return e;
     const dim3 g(multi_grid(ncit, max_blocks)), b(kBlock);
-    hipLaunchKernelGGL(multi_cuckoo_probe_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
-    hipLaunchKernelGGL(multi_cuckoo_evict_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
-    hipLaunchKernelGGL(multi_cuckoo_scrub_kernel, g, b, 0, s, d.d_ctabs, d.d_citems, (uint32_t)ncit);
+    const MultiCuckoo* ct = reinterpret_cast<const MultiCuckoo*>(dv + o_ctabs);
+    const uint64_t* ci = reinterpret_cast<const uint64_t*>(dv + o_citems);
+    hipLaunchKernelGGL(multi_cuckoo_probe_kernel, g, b, 0, s, ct, ci, (uint32_t)ncit);
+    hipLaunchKernelGGL(multi_cuckoo_evict_kernel, g, b, 0, s, ct, ci, (uint32_t)ncit);
+    hipLaunchKernelGGL(multi_cuckoo_scrub_kernel, g, b, 0, s, ct, ci, (uint32_t)ncit);
+  }
+  if (nqit) launch_query(reinterpret_cast<const MultiQuery*>(dv + o_qtabs), nq, nqit, max_blocks, s);
+  return hipGetLastError();
+}
+
+hipError_t multi_query_once(const MultiQuerySpec* qs, uint32_t nq, uint32_t max_blocks, hipStream_t s) {
+  const uint64_t max_waves = (uint64_t)max_blocks * (kBlock / kWave);
+  std::vector<MultiQuery> tabs(nq);
+  const uint64_t nit = fill_query(qs, nq, max_waves, tabs.data());
+  if (!nit) return hipSuccess;
+  void* base = nullptr;
+  hipError_t e = hipMalloc(&base, sizeof(MultiQuery) * nq);
+  if (e != hipSuccess) return e;
+  e = hipMemcpyAsync(base, tabs.data(), sizeof(MultiQuery) * nq, hipMemcpyHostToDevice, s);
+  if (e == hipSuccess) {
+    launch_query(static_cast<const MultiQuery*>(base), nq, nit, max_blocks, s);
     e = hipGetLastError();
   }
-  return e;
+  const hipError_t e2 = hipStreamSynchronize(s);
+  (void)hipFree(base);
+  return e != hipSuccess ? e : e2;
 }
 
 }  // namespace ht

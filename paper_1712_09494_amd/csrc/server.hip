@@ -18,8 +18,9 @@
 //     tables and up to `group_keys` keys (so small requests are not held
 //     behind large ones); its find-or-puts run as many-table launches (one
 //     for the bucketed tables, three phase launches for the Cuckoo tables),
-//     its queries as their own kernels, all on the group's stream between
-//     the host-to-device copies and the device-to-host copies;
+//     its queries as one many-table query launch (a query large enough to
+//     fill the device alone gets its own launch), all on the group's stream
+//     between the host-to-device copies and the device-to-host copies;
 //   - overlap: groups on different stream slots run concurrently.
 // The sequential baseline runs one request at a time, waiting for each.
 #include <algorithm>
@@ -252,6 +253,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
   };
   std::vector<MultiSpec> specs;
   std::vector<MultiCuckooSpec> cspecs;
+  std::vector<MultiQuerySpec> qspecs;
   specs.reserve(s->cfg.merge);
   cspecs.reserve(s->cfg.merge);
   int err = HT_OK;
@@ -331,6 +333,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
       hipStream_t st = sl.stream;
       specs.clear();
       cspecs.clear();
+      qspecs.clear();
       for (size_t k = 0; k < sl.reqs.size() && err == HT_OK; ++k) {
         const ht_request& r = reqs[sl.reqs[k]];
         if (!r.n) continue;
@@ -359,12 +362,16 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
         } else if (r.op == HT_OP_FIND_OR_PUT) {
           err = do_find_or_put(tb, dk, r.n, dflag, st);
         } else {
-          err = do_query(tb, dk, r.n, dflag, st);
+          const MultiQuerySpec q{launch_view(tb), dk, dflag, r.n, tb->cfg.kind == HT_CUCKOO};
+          if (s->cfg.merge > 1 && !multi_query_alone(q, s->grid))
+            qspecs.push_back(q);
+          else
+            err = do_query(tb, dk, r.n, dflag, st);
         }
       }
-      if (err == HT_OK && !(specs.empty() && cspecs.empty())) {
-        hipError_t e = multi_dyn_launch(sl.dyn, specs.data(), (uint32_t)specs.size(), cspecs.data(),
-                                        (uint32_t)cspecs.size(), s->grid, st);
+      if (err == HT_OK && !(specs.empty() && cspecs.empty() && qspecs.empty())) {
+        hipError_t e = multi_dyn_issue(sl.dyn, specs.data(), (uint32_t)specs.size(), cspecs.data(),
+                                       (uint32_t)cspecs.size(), qspecs.data(), (uint32_t)qspecs.size(), s->grid, st);
         if (e != hipSuccess) err = hip_fail(e, "serving many-table launch");
         ++merged;
       }

@@ -735,6 +735,46 @@ int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys, cons
   return rc;
 }
 
+int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint64_t* n,
+                   uint8_t* const* d_out_found, uint32_t ntables, hipStream_t s) {
+  if (ntables == 0) return HT_OK;
+  if (!t || !d_keys || !n || !d_out_found) return fail(HT_EINVAL, "NULL argument array");
+  if (ntables > (1u << 23)) return fail(HT_EINVAL, "too many tables in one call");
+  std::vector<MultiQuerySpec> qs;
+  for (uint32_t i = 0; i < ntables; ++i) {
+    int rc = check_table(t[i]);
+    if (rc) return rc;
+    if (n[i] && (!d_keys[i] || !d_out_found[i])) return fail(HT_EINVAL, "keys or flags is NULL");
+    if (n[i] >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
+    if (is_scripted(t[i])) return fail(HT_EINVAL, "scripted-hash tables are not supported by the multi-table call");
+    if (t[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables are not supported by the multi-table call");
+  }
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  const uint32_t grid = device_cus(dev) * 8;
+  for (uint32_t i = 0; i < ntables; ++i) {
+    if (!n[i]) continue;
+    MultiQuerySpec q{};
+    q.t = launch_view(t[i]);
+    q.keys = d_keys[i];
+    q.out = d_out_found[i];
+    q.n = n[i];
+    q.cuckoo = t[i]->cfg.kind == HT_CUCKOO;
+    if (multi_query_alone(q, grid)) {
+      int rc = do_query(t[i], d_keys[i], n[i], d_out_found[i], s);
+      if (rc) return rc;
+    } else {
+      qs.push_back(q);
+    }
+  }
+  {
+    KernelTimer kt("multi_query", s);
+    HT_HIP(multi_query_once(qs.data(), (uint32_t)qs.size(), grid, s));
+  }
+  HT_HIP(hipStreamSynchronize(s));
+  return HT_OK;
+}
+
 int ht_sync_status(ht_table* t, hipStream_t s) {
   int rc = check_table(t);
   if (rc) return rc;

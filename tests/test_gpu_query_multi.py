@@ -1,0 +1,174 @@
+"""GPU: queries of many tables in one launch equal the oracle's membership
+(exact), for both designs and every table option, including members held in
+the stash and on the overflow list and the all-ones key."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import Oracle  # noqa: E402
+from paper_1712_09494_amd import binding as b  # noqa: E402
+from paper_1712_09494_amd import inputs  # noqa: E402
+from parity import check_query_r1  # noqa: E402
+
+pytestmark = pytest.mark.gpu
+
+KINDS = [
+    ("bucketed", dict(bucket_slots=8)),
+    ("bucketed", dict(bucket_slots=16)),
+    ("bucketed", dict(bucket_slots=32, nhash=2)),
+    ("bucketed", dict(bucket_slots=64, nhash=4)),
+    ("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+    ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)),
+    ("cuckoo", dict()),
+    ("cuckoo", dict(nhash=4)),
+    ("cuckoo", dict(flags=b.HT_FLAG_CUCKOO_PAPER_ORDER)),
+    ("cuckoo", dict(nhash=2)),
+]
+
+
+def dev(a):
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int64)).cuda()
+
+
+def fill(seed, ntables, max_log=16, lf=0.6):
+    """Tables of every kind, each filled with its own batch; returns the
+    tables, their oracles and the query batches (members, non-members and
+    the all-ones key mixed)."""
+    rng = np.random.default_rng(seed)
+    tables, oracles, queries = [], [], []
+    for i in range(ntables):
+        kind, kw = KINDS[i % len(KINDS)]
+        kw = dict(kw)
+        kw.setdefault("nhash", 3)
+        cap = int(round(2 ** rng.uniform(6, max_log)))
+        distinct = max(1, int(lf * cap))
+        keys = inputs.random_sequence(distinct + distinct // 3, distinct, seed=seed * 1000 + i)
+        if i % 3 == 0:
+            keys[:: 89] = b.EMPTY
+        t = b.Table(kind, capacity=cap, **kw)
+        o = Oracle()
+        if keys.size:
+            t.find_or_put(dev(keys))
+            o.find_or_put(keys)
+        nq = int(rng.integers(0, 3 * distinct + 2))
+        q = inputs.uniform_keys(nq, seed=seed * 1000 + 500 + i)
+        if keys.size and nq:
+            take = rng.random(nq) < 0.5
+            q[take] = keys[rng.integers(0, keys.size, int(take.sum()))]
+        if i % 4 == 1 and nq:
+            q[:: 61] = b.EMPTY
+        if i % 13 == 7:
+            q = q[:0]                       # an empty batch
+        tables.append(t)
+        oracles.append(o)
+        queries.append(q)
+    return tables, oracles, queries
+
+
+@pytest.mark.parametrize("seed,ntables", [(1, 10), (2, 57), (3, 300)])
+def test_query_multi_equals_oracle(seed, ntables):
+    tables, oracles, queries = fill(seed, ntables)
+    outs = b.query_multi(tables, [dev(q) for q in queries])
+    for i, t in enumerate(tables):
+        check_query_r1(outs[i].cpu().numpy(), oracles[i].query(queries[i]), f"table {i}")
+        t.close()
+
+
+def test_query_multi_matches_single_queries_large():
+    """Batches of a few million keys (each gets a launch of its own) beside
+    small ones that share a launch."""
+    tables, oracles, queries = [], [], []
+    for i, (kind, kw) in enumerate([("bucketed", dict(bucket_slots=16)), ("cuckoo", dict()),
+                                    ("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE))]):
+        n = (1 << 21) + 4097 * (i + 1)
+        keys = inputs.random_sequence(n, int(0.8 * n), seed=40 + i)
+        t = b.Table(kind, capacity=n * 5 // 4, nhash=3, **kw)
+        t.find_or_put(dev(keys))
+        q = inputs.uniform_keys(3 * n // 2 + 17 * i, seed=50 + i)
+        q[::2] = keys[: q[::2].size]
+        tables.append(t)
+        queries.append(q)
+        oracles.append(Oracle(keys))
+    for i in range(3):
+        keys = inputs.random_sequence(5000 + i, 4000, seed=60 + i)
+        t = b.Table("cuckoo" if i == 1 else "bucketed", capacity=8192, nhash=3)
+        t.find_or_put(dev(keys))
+        q = np.concatenate([keys[:2000], inputs.uniform_keys(3000, seed=70 + i)])
+        tables.append(t)
+        queries.append(q)
+        oracles.append(Oracle(keys))
+    outs = b.query_multi(tables, [dev(q) for q in queries])
+    for i, t in enumerate(tables):
+        single = t.query(dev(queries[i])).cpu().numpy()
+        got = outs[i].cpu().numpy()
+        check_query_r1(got, oracles[i].query(queries[i]), f"table {i}")
+        check_query_r1(got, single, f"table {i} vs single query")
+        t.close()
+
+
+def test_query_multi_many_mid_size_batches():
+    """Batches just below the size that gets a launch of its own, enough of
+    them that the shared launch has several items per wave."""
+    tables, oracles, queries = [], [], []
+    kinds = [("cuckoo", dict(), 120000), ("bucketed", dict(bucket_slots=8), 120000),
+             ("bucketed", dict(bucket_slots=16), 100000), ("bucketed", dict(bucket_slots=64), 20000)]
+    for i in range(100):
+        kind, kw, n = kinds[i % len(kinds)]
+        n = n - 977 * (i % 7)
+        keys = inputs.random_sequence(n // 2, n // 3, seed=300 + i)
+        t = b.Table(kind, capacity=n, nhash=3, **kw)
+        t.find_or_put(dev(keys))
+        q = inputs.uniform_keys(n, seed=700 + i)
+        q[1::2] = keys[: q[1::2].size]
+        tables.append(t)
+        oracles.append(Oracle(keys))
+        queries.append(q)
+    outs = b.query_multi(tables, [dev(q) for q in queries])
+    for i, t in enumerate(tables):
+        check_query_r1(outs[i].cpu().numpy(), oracles[i].query(queries[i]), f"table {i}")
+        t.close()
+
+
+@pytest.mark.parametrize("kind,B", [("bucketed", 8), ("bucketed", 64), ("cuckoo", 0)])
+def test_query_multi_stash_and_overflow(kind, B):
+    """Members on the stash and the overflow list are found by the
+    many-table query as by the single-table one."""
+    kw = dict(bucket_slots=B) if kind == "bucketed" else {}
+    t = b.Table(kind, capacity=64, nhash=1, stash_slots=16, overflow_slots=4096, bucket_walk=1, **kw)
+    keys = inputs.uniform_keys(600, seed=7)
+    t.find_or_put(dev(keys))
+    st = t.stats()
+    assert st["stash_count"] > 0 and st["overflow_count"] > 0 and st["lost"] == 0
+    q = np.concatenate([keys, inputs.uniform_keys(600, seed=8)])
+    other = b.Table("cuckoo", capacity=1024)
+    other.find_or_put(dev(keys[:100]))
+    outs = b.query_multi([t, other], [dev(q), dev(q)])
+    check_query_r1(outs[0].cpu().numpy(), Oracle(keys).query(q), "small table")
+    check_query_r1(outs[1].cpu().numpy(), Oracle(keys[:100]).query(q), "other table")
+    t.close()
+    other.close()
+
+
+def test_query_multi_same_table_twice():
+    t = b.Table("bucketed", capacity=4096)
+    keys = inputs.uniform_keys(2000, seed=9)
+    t.find_or_put(dev(keys))
+    q1 = keys[:500]
+    q2 = inputs.uniform_keys(700, seed=10)
+    outs = b.query_multi([t, t], [dev(q1), dev(q2)])
+    assert outs[0].cpu().numpy().all()
+    check_query_r1(outs[1].cpu().numpy(), Oracle(keys).query(q2), "second batch")
+    t.close()
+
+
+def test_query_multi_rejects_bad_arguments():
+    k = dev(inputs.uniform_keys(10, seed=1))
+    ts = b.Table("cuckoo", capacity=64, flags=b.HT_FLAG_SCRIPTED_HASH)
+    with pytest.raises(b.HtError):
+        b.query_multi([ts], [k])
+    tv = b.Table("bucketed", capacity=64, key_words=2)
+    with pytest.raises(b.HtError):
+        b.query_multi([tv], [k])
+    ts.close()
+    tv.close()

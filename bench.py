@@ -54,7 +54,7 @@ def parse():
     ap.add_argument("--no-served", action="store_true")
     ap.add_argument("--served-only", action="store_true",
                     help="only run the served request-loop measurement")
-    ap.add_argument("--served-requests", type=int, default=1024)
+    ap.add_argument("--served-requests", type=int, default=4096)
     ap.add_argument("--no-bfs", action="store_true")
     ap.add_argument("--no-lds", action="store_true", help="skip the LDS occupancy ablation")
     ap.add_argument("--no-vectors", action="store_true", help="skip the state-vector tables")
@@ -894,7 +894,7 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
     return res
 
 
-def run_served(b, inputs, torch, dev, nreq=1024, ntables=64, slots_log2=24):
+def run_served(b, inputs, torch, dev, nreq=4096, ntables=64, slots_log2=24):
     """Served request loop: 64 resident tables of 2^24 slots (2^30 slots,
     8 GiB), `nreq` requests of log-uniform sizes 2^8..2^20 (70% keys from a
     synthetic BFS successor stream, 30% random; half find-or-put, half

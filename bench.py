@@ -868,29 +868,43 @@ def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
 
 def run_bfs(b, inputs, torch, levels=7, lf=0.7):
     """BFS-key workload: breadth-first exploration of the synthetic 16-process
-    model (seed 1) on the GPU, each level's successor batch (duplicates
-    included) one find-or-put into a table sized for the final state count at
-    load factor 0.7.  Successor generation and frontier selection are outside
-    the timed find-or-put calls."""
+    model (seed 1) on the GPU into a table sized for the final state count at
+    load factor 0.7.  Split levels: each level's successor batch (duplicates
+    included) is one find-or-put; `fop_mops` times only those calls
+    (generation and frontier selection outside).  Every design also reports
+    the device time of whole levels (`level_ms`: split = count, scan, write,
+    find-or-put, select; fused = generation and find-or-put in one kernel,
+    scan, write of the new states) and the rate of successors through whole
+    levels (`level_mops`)."""
     final_states = 121210369          # states reached after level 6 (seed 1)
     res = {"levels": levels, "load_factor": lf, "designs": {}}
-    for kind_name, kind, kw in (("bucketed", "bucketed", dict(bucket_slots=8)),
-                                ("bucketed_one_lane", "bucketed",
-                                 dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
-                                ("cuckoo", "cuckoo", {})):
+    for kind_name, kind, kw, mode in (
+            ("bucketed", "bucketed", dict(bucket_slots=8), b.HT_BFS_SPLIT),
+            ("bucketed_one_lane", "bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
+             b.HT_BFS_SPLIT),
+            ("bucketed_fused", "bucketed", dict(bucket_slots=8), b.HT_BFS_FUSED),
+            ("cuckoo", "cuckoo", {}, b.HT_BFS_SPLIT)):
         with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=3, **kw) as t:
-            r = t.bfs_explore(inputs.BfsModel(1), levels)
+            r = b.ht_bfs_explore_ex(t.handle, inputs.BfsModel(1), levels, mode)
             keys = sum(r["batch_sizes"])
             ms = sum(r["fop_ms"])
-            res["designs"][kind_name] = {
-                "batch_sizes": r["batch_sizes"], "new_counts": r["new_counts"],
-                "states": 1 + sum(r["new_counts"]),
-                "fop_ms": [round(x, 3) for x in r["fop_ms"]],
-                "fop_mops_per_level": [round(n / max(x, 1e-9) / 1e3, 1) for n, x in zip(r["batch_sizes"], r["fop_ms"])],
-                "fop_mops": round(keys / ms / 1e3, 1),
-                "occurrences_per_state": round(keys / max(1, sum(r["new_counts"])), 2)}
-        log(f"[bench] bfs {kind_name}: {res['designs'][kind_name]['fop_mops']} Mops/s, "
-            f"states {res['designs'][kind_name]['states']}")
+            lms = sum(r["level_ms"])
+            d = {"mode": "fused" if mode == b.HT_BFS_FUSED else "split",
+                 "batch_sizes": r["batch_sizes"], "new_counts": r["new_counts"],
+                 "states": 1 + sum(r["new_counts"]),
+                 "level_ms": [round(x, 3) for x in r["level_ms"]],
+                 "level_mops": round(keys / lms / 1e3, 1),
+                 "occurrences_per_state": round(keys / max(1, sum(r["new_counts"])), 2)}
+            if mode == b.HT_BFS_SPLIT:
+                d["fop_ms"] = [round(x, 3) for x in r["fop_ms"]]
+                d["fop_mops_per_level"] = [round(n / max(x, 1e-9) / 1e3, 1)
+                                           for n, x in zip(r["batch_sizes"], r["fop_ms"])]
+                d["fop_mops"] = round(keys / ms / 1e3, 1)
+            else:
+                d["fused_kernel_ms"] = [round(x, 3) for x in r["fop_ms"]]
+            res["designs"][kind_name] = d
+        log(f"[bench] bfs {kind_name}: " + (f"find-or-put {d['fop_mops']} Mops/s, " if "fop_mops" in d else "")
+            + f"whole levels {d['level_mops']} Mops/s ({lms:.2f} ms), states {d['states']}")
     return res
 
 

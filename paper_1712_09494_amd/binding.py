@@ -149,6 +149,8 @@ def pack_bfs_model(model) -> HtBfsModel:
     return m
 
 
+HT_BFS_SPLIT = 0
+HT_BFS_FUSED = 1
 HT_OP_FIND_OR_PUT = 1
 HT_OP_QUERY = 2
 
@@ -205,6 +207,8 @@ _PROTOS = {
     "ht_last_error": (C.c_char_p, []),
     "ht_bfs_explore": (C.c_int, [_vp, C.POINTER(HtBfsModel), _u64, _u32, C.POINTER(_u64), C.POINTER(_u64),
                                  C.POINTER(C.c_double), _vp]),
+    "ht_bfs_explore_ex": (C.c_int, [_vp, C.POINTER(HtBfsModel), _u64, _u32, _u32, C.POINTER(_u64),
+                                    C.POINTER(_u64), C.POINTER(C.c_double), C.POINTER(C.c_double), _vp]),
     "ht_server_config_default": (None, [C.POINTER(HtServerConfig)]),
     "ht_server_create": (C.c_int, [C.POINTER(_vp), _u32, C.POINTER(HtServerConfig), C.POINTER(_vp)]),
     "ht_server_run": (C.c_int, [_vp, C.POINTER(HtRequest), _u32, C.POINTER(HtServerStats)]),
@@ -599,7 +603,9 @@ class Table:
     def reserve(self, max_batch: int) -> None:
         ht_reserve(self.handle, max_batch)
 
-    def bfs_explore(self, model, levels: int, initial: int = 0, stream=None) -> dict:
+    def bfs_explore(self, model, levels: int, initial: int = 0, stream=None, fused: bool = False) -> dict:
+        if fused:
+            return ht_bfs_explore_ex(self.handle, model, levels, HT_BFS_FUSED, initial, stream)
         return ht_bfs_explore(self.handle, model, levels, initial, stream)
 
 
@@ -614,6 +620,22 @@ def ht_bfs_explore(h: int, model, levels: int, initial: int = 0, stream=None) ->
     done = [i for i in range(levels) if bs[i] or i == 0]
     return {"batch_sizes": [int(bs[i]) for i in range(levels)], "new_counts": [int(nc[i]) for i in range(levels)],
             "fop_ms": [float(ms[i]) for i in range(levels)], "levels": len(done)}
+
+
+def ht_bfs_explore_ex(h: int, model, levels: int, mode: int = 0, initial: int = 0, stream=None) -> dict:
+    """ht_bfs_explore with a mode (HT_BFS_SPLIT or HT_BFS_FUSED) and the
+    device time of each whole level (level_ms)."""
+    m = pack_bfs_model(model)
+    bs = (_u64 * max(levels, 1))()
+    nc = (_u64 * max(levels, 1))()
+    ms = (C.c_double * max(levels, 1))()
+    lv = (C.c_double * max(levels, 1))()
+    _check(load().ht_bfs_explore_ex(h, C.byref(m), initial & EMPTY, levels, mode, bs, nc, ms, lv,
+                                    _stream_handle(stream)), "ht_bfs_explore_ex")
+    done = [i for i in range(levels) if bs[i] or i == 0]
+    return {"batch_sizes": [int(bs[i]) for i in range(levels)], "new_counts": [int(nc[i]) for i in range(levels)],
+            "fop_ms": [float(ms[i]) for i in range(levels)], "level_ms": [float(lv[i]) for i in range(levels)],
+            "levels": len(done)}
 
 
 class Server:

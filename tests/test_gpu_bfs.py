@@ -67,3 +67,85 @@ def test_bfs_full_size_seed2():
         r = t.bfs_explore(inputs.BfsModel(2), 7)
         v = list(1 + np.cumsum(r["new_counts"]))
         assert v[5] == g["visited_after_level5"] and v[6] == g["visited_after_level6"]
+
+
+FUSED = [dict(bucket_slots=8), dict(bucket_slots=16), dict(bucket_slots=64, nhash=2),
+         dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)]
+
+
+def oracle_bfs(model, initial, levels):
+    o = Oracle([initial])
+    frontier = np.array([initial], dtype=np.uint64)
+    sizes, news = [], []
+    for _ in range(levels):
+        batch = model.successors(frontier)
+        f = o.find_or_put(batch)
+        frontier = batch[f == 1]
+        sizes.append(batch.size)
+        news.append(int(f.sum()))
+    return o, sizes, news
+
+
+@pytest.mark.parametrize("kw", FUSED)
+def test_bfs_fused_levels_match_oracle(kw):
+    """Fused levels (generation and find-or-put in one kernel) give the
+    oracle's batch sizes, new counts and visited set."""
+    model = inputs.BfsModel(1)
+    o, sizes, news = oracle_bfs(model, 0, 5)
+    kw = dict(kw)
+    kw.setdefault("nhash", 3)
+    with b.Table("bucketed", capacity=int(np.ceil(o.size / 0.7)), **kw) as t:
+        r = t.bfs_explore(model, 5, fused=True)
+        assert r["batch_sizes"] == sizes
+        assert r["new_counts"] == news
+        assert all(x > 0 for x in r["level_ms"])
+        assert np.array_equal(np.sort(b.u64(t.dump())), o.dump())
+        assert t.size() == o.size
+
+
+def test_bfs_fused_from_all_ones_state():
+    """The all-ones state (the table's empty marker) as the initial state:
+    fused and split levels agree with the oracle."""
+    model = inputs.BfsModel(2)
+    init = int(b.EMPTY)
+    o, sizes, news = oracle_bfs(model, init, 4)
+    for fused in (False, True):
+        with b.Table("bucketed", capacity=int(np.ceil(o.size / 0.7)), nhash=3, bucket_slots=8) as t:
+            r = t.bfs_explore(model, 4, initial=init, fused=fused)
+            assert r["batch_sizes"] == sizes, fused
+            assert r["new_counts"] == news, fused
+            assert np.array_equal(np.sort(b.u64(t.dump())), o.dump()), fused
+            assert t.query(torch.tensor([-1], dtype=torch.int64, device="cuda")).item() == 1
+
+
+def test_bfs_fused_full_size_seed1():
+    g = golden()["seed1"]
+    visited = g["visited_after"]
+    with b.Table("bucketed", capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, bucket_slots=8) as t:
+        r = t.bfs_explore(inputs.BfsModel(1), 7, fused=True)
+        assert r["batch_sizes"] == g["batch_sizes"]
+        assert list(1 + np.cumsum(r["new_counts"])) == visited
+        assert t.size() == visited[-1]
+        assert t.sync_status() == b.HT_OK
+
+
+def test_bfs_split_level_times():
+    """The mode-taking call in split mode equals the plain call and reports
+    per-level device times that cover the find-or-put."""
+    model = inputs.BfsModel(1)
+    with b.Table("cuckoo", capacity=1 << 16, nhash=3) as t1, b.Table("cuckoo", capacity=1 << 16, nhash=3) as t2:
+        r1 = t1.bfs_explore(model, 4)
+        r2 = b.ht_bfs_explore_ex(t2.handle, model, 4, b.HT_BFS_SPLIT)
+        assert r1["batch_sizes"] == r2["batch_sizes"] and r1["new_counts"] == r2["new_counts"]
+        assert all(lv >= f > 0 for lv, f in zip(r2["level_ms"], r2["fop_ms"]))
+
+
+def test_bfs_fused_rejects_other_tables():
+    model = inputs.BfsModel(1)
+    for kw in (dict(kind="cuckoo"), dict(kind="bucketed", flags=b.HT_FLAG_SCRIPTED_HASH)):
+        with b.Table(capacity=1024, **kw) as t:
+            with pytest.raises(b.HtError):
+                t.bfs_explore(model, 2, fused=True)
+    with b.Table("bucketed", capacity=1024) as t:
+        with pytest.raises(b.HtError):
+            b.ht_bfs_explore_ex(t.handle, model, 2, 7)

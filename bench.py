@@ -317,15 +317,21 @@ def kernel_bytes(name, n, d_new, c, bucket_slots):
     return None
 
 
+# Sources that define or launch the kernels of the counted workload (the
+# single-table find-or-put kernels of both designs and what they include).
+COUNTED_SOURCES = ("ht_device.h", "bucketed_dev.h", "bucketed.hip", "cuckoo_dev.h", "cuckoo.hip", "runtime.h",
+                   "table.hip", "util.hip")
+
+
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources, to tell whether committed counters are current."""
-    import glob
+    """sha256 over the HIP sources of the counted kernels, to tell whether
+    committed counters are current."""
     import hashlib
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1712_09494_amd", "csrc")
-    for p in sorted(glob.glob(os.path.join(csrc, "*.hip")) + glob.glob(os.path.join(csrc, "*.h"))):
-        h.update(os.path.basename(p).encode())
-        with open(p, "rb") as f:
+    for name in sorted(COUNTED_SOURCES):
+        h.update(name.encode())
+        with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
 

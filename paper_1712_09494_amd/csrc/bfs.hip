@@ -166,6 +166,15 @@ struct Buf {
   }
 };
 
+// Events of one exploration, destroyed on every return path.
+struct Events {
+  hipEvent_t e[6] = {};
+  ~Events() {
+    for (auto& x : e)
+      if (x) (void)hipEventDestroy(x);
+  }
+};
+
 }  // namespace
 
 // Device time between two recorded events, in ms.
@@ -204,9 +213,11 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
   const DevTable dt = launch_view(t);
   uint64_t nf = 1;
   // ev[0..1]: first span of a level; ev[2..3]: second span (a host round trip
-  // between them reads sizes); ev[4]: end of the find-or-put (or fused pass)
-  hipEvent_t ev[6] = {};
-  for (auto& e : ev) HT_HIP(hipEventCreate(&e));
+  // between them reads sizes); ev[4]: end of the find-or-put (or fused pass);
+  // ev[5]: start of the find-or-put
+  Events evs;
+  hipEvent_t* ev = evs.e;
+  for (int i = 0; i < 6; ++i) HT_HIP(hipEventCreate(&ev[i]));
   for (uint32_t L = 0; L < levels && nf && rc == HT_OK; ++L) {
     rc = counts.ensure(nf * 8);
     if (!rc) rc = offsets.ensure(nf * 8);
@@ -291,8 +302,6 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
     std::swap(frontier.bytes, next.bytes);
     nf = nnew;
   }
-  for (auto& e : ev)
-    if (e) (void)hipEventDestroy(e);
   (void)hipStreamSynchronize(s);
   return rc;
 }

@@ -735,45 +735,6 @@ def run_probes(b, torch, dev, stream):
     return res
 
 
-def batched_workload(inputs, ntables=256, lf=0.6):
-    """256 tables with capacities log-uniform in [2^10, 2^22), each with
-    floor(lf * cap) distinct keys: even tables random keys, odd tables a
-    prefix of one synthetic BFS successor stream (16-process model, seed 1,
-    levels 0-4) holding that many distinct keys (duplicates included; the
-    stream holds 2,049,037 distinct states, which caps the largest BFS
-    tables)."""
-    from paper_1712_09494_amd.inputs import SplitMix64, BfsModel
-    r = SplitMix64(0x1712094940 + 3)
-    caps = []
-    for _ in range(ntables):
-        u = 10 + 12 * (r.next() / 2.0 ** 64)
-        caps.append(int(round(2 ** u)))
-    model = BfsModel(1)
-    frontier = np.array([0], dtype=np.uint64)
-    parts = []
-    seen = np.array([0], dtype=np.uint64)
-    for _ in range(5):
-        batch = model.successors(frontier)
-        parts.append(batch)
-        u, first = np.unique(batch, return_index=True)
-        new = ~np.isin(u, seen)
-        frontier = batch[np.sort(first[new])]
-        seen = np.union1d(seen, u[new])
-    stream = np.concatenate(parts)
-    _, first = np.unique(stream, return_index=True)
-    first = np.sort(first)
-    keys, distinct = [], []
-    for t, cap in enumerate(caps):
-        d = max(1, int(lf * cap))
-        if t % 2 == 0:
-            keys.append(inputs.uniform_keys(d, seed=0x1712094940 + 4 + t))
-        else:
-            d = min(d, first.size)
-            keys.append(stream[: int(first[d - 1]) + 1])
-        distinct.append(d)
-    return caps, keys, distinct
-
-
 def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
     """Many tables: 256 plain per-table calls vs one persistent launch (plan)
     vs the plan's launch replayed from a captured HIP graph; then queries of
@@ -781,7 +742,7 @@ def run_batched(b, inputs, torch, dev, stream, ntables=256, lf=0.6, reps=3):
     host wall clock, Python included)."""
     from paper_1712_09494_amd import tune
     t0 = time.time()
-    caps, keys, distinct = batched_workload(inputs, ntables, lf)
+    caps, keys, distinct = inputs.batched_workload(ntables, lf)
     kd = [torch.from_numpy(k.view(np.int64)).to(dev) for k in keys]
     outs = [torch.empty(k.numel(), dtype=torch.uint8, device=dev) for k in kd]
     total = int(sum(k.numel() for k in kd))

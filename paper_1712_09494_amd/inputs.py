@@ -403,6 +403,45 @@ def successor_stream(model: "BfsModel", min_keys: int, start_states=(0,)) -> np.
     return np.concatenate(out) if out else np.zeros(0, dtype=np.uint64)
 
 
+def batched_workload(ntables: int = 256, lf: float = 0.6):
+    """Many-table workload: `ntables` capacities log-uniform in [2^10, 2^22)
+    (splitmix64 stream of seed SEED_BASE + 3), each table with
+    floor(lf * cap) distinct keys: even tables random keys (seed SEED_BASE +
+    4 + t), odd tables a prefix of one synthetic BFS successor stream
+    (16-process model, seed 1, levels 0-4, duplicates included) holding that
+    many distinct keys (the stream holds 2,049,037 distinct states, which
+    caps the largest BFS tables).  Returns (caps, keys, distinct counts)."""
+    r = SplitMix64(SEED_BASE + 3)
+    caps = []
+    for _ in range(ntables):
+        u = 10 + 12 * (r.next() / 2.0 ** 64)
+        caps.append(int(round(2 ** u)))
+    model = BfsModel(1)
+    frontier = np.array([0], dtype=np.uint64)
+    parts = []
+    seen = np.array([0], dtype=np.uint64)
+    for _ in range(5):
+        batch = model.successors(frontier)
+        parts.append(batch)
+        u, first = np.unique(batch, return_index=True)
+        new = ~np.isin(u, seen)
+        frontier = batch[np.sort(first[new])]
+        seen = np.union1d(seen, u[new])
+    stream = np.concatenate(parts)
+    _, first = np.unique(stream, return_index=True)
+    first = np.sort(first)
+    keys, distinct = [], []
+    for t, cap in enumerate(caps):
+        d = max(1, int(lf * cap))
+        if t % 2 == 0:
+            keys.append(uniform_keys(d, seed=SEED_BASE + 4 + t))
+        else:
+            d = min(d, first.size)
+            keys.append(stream[: int(first[d - 1]) + 1])
+        distinct.append(d)
+    return caps, keys, distinct
+
+
 def served_trace(nreq: int, ntables: int, log_min: float = 8, log_max: float = 20, rate: float = 0.0,
                  seed: int = SEED_BASE + 5, bfs_frac: float = 0.7, query_frac: float = 0.5,
                  stream: np.ndarray | None = None):

@@ -134,3 +134,18 @@ def test_vector_generators(w, structured):
     if structured:
         # most vectors share their later words with many others
         assert np.unique(v[:, -1]).size < 50000 // 10
+
+
+def test_batched_workload_shape():
+    """The many-table workload: 256 capacities in [2^10, 2^22], each table's
+    batch holding exactly its stated number of distinct keys (random tables
+    without repeats, BFS tables a stream prefix with repeats)."""
+    caps, keys, distinct = inputs.batched_workload()
+    assert len(caps) == len(keys) == len(distinct) == 256
+    assert all(1 << 10 <= c <= 1 << 22 for c in caps)
+    for t in list(range(0, 256, 17)) + [1, 3]:
+        assert np.unique(keys[t]).size == distinct[t]
+        assert distinct[t] <= max(1, int(0.6 * caps[t]))
+        if t % 2 == 0:
+            assert keys[t].size == distinct[t]
+    assert sum(k.size for k in keys) > sum(distinct)     # the BFS prefixes repeat states

@@ -840,9 +840,11 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
     included) is one find-or-put; `fop_mops` times only those calls
     (generation and frontier selection outside).  Every design also reports
     the device time of whole levels (`level_ms`: split = count, scan, write,
-    find-or-put, select; fused = generation and find-or-put in one kernel,
-    scan, write of the new states) and the rate of successors through whole
-    levels (`level_mops`)."""
+    find-or-put, select; fused = generation joined with the find-or-put --
+    one kernel for bucketed tables; successor counts, scan, fused probe and
+    placement, evict and scrub for Cuckoo tables -- then a scan and the write
+    of the new states) and the rate of successors through whole levels
+    (`level_mops`)."""
     final_states = 121210369          # states reached after level 6 (seed 1)
     res = {"levels": levels, "load_factor": lf, "designs": {}}
     for kind_name, kind, kw, mode in (
@@ -850,7 +852,8 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
             ("bucketed_one_lane", "bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
              b.HT_BFS_SPLIT),
             ("bucketed_fused", "bucketed", dict(bucket_slots=8), b.HT_BFS_FUSED),
-            ("cuckoo", "cuckoo", {}, b.HT_BFS_SPLIT)):
+            ("cuckoo", "cuckoo", {}, b.HT_BFS_SPLIT),
+            ("cuckoo_fused", "cuckoo", {}, b.HT_BFS_FUSED)):
         with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=3, **kw) as t:
             r = b.ht_bfs_explore_ex(t.handle, inputs.BfsModel(1), levels, mode)
             keys = sum(r["batch_sizes"])

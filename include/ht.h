@@ -321,25 +321,29 @@ int ht_bfs_explore(ht_table* t, const ht_bfs_model* model, uint64_t initial, uin
 
 enum {
   HT_BFS_SPLIT = 0,   /* generate the batch, find-or-put it, select the new keys */
-  HT_BFS_FUSED = 1    /* generate and find-or-put in one kernel (bucketed only) */
+  HT_BFS_FUSED = 1    /* generate and find-or-put without storing the batch */
 };
 
 /* ht_bfs_explore with the level's kernels chosen by `mode`.  HT_BFS_SPLIT is
  * ht_bfs_explore.  HT_BFS_FUSED joins successor generation and hash table
- * access in one kernel, as GPUexplore does (Sec. 3.2 and 7): a lane takes a
- * frontier state, generates its successors in registers in the same order
- * and find-or-puts each (one lane per key, the probe of
- * HT_FLAG_BUCKETED_ONE_LANE), recording which were new; a second kernel
- * writes the new ones, so the successor batch is never stored.  Needs a
- * bucketed table without HT_FLAG_SCRIPTED_HASH (HT_EINVAL otherwise).  Both
- * modes give the same batch sizes, new counts and visited set; within a
- * level the next frontier holds the same states (which copy of a repeated
- * successor counts as new, and so its place, may differ).  Extra host array
- * (may be NULL): level_ms[L] the device time of all of level L's kernels
- * (split: count, scan, write, find-or-put, select; fused: fused pass, scan,
- * write), without the host round trip that reads the level's sizes.  In
- * fused mode fop_ms[L] is the fused kernel's time.  Allocates its buffers;
- * synchronises. */
+ * access, as GPUexplore does (Sec. 3.2 and 7): a lane takes a frontier state,
+ * generates its successors in registers in the same order and find-or-puts
+ * each, recording which were new; a last kernel writes the new ones, so the
+ * successor batch is never stored.  Bucketed tables: one kernel, one lane per
+ * key (the probe of HT_FLAG_BUCKETED_ONE_LANE).  Cuckoo tables: the exact
+ * insertion's phases stay separate kernels (Sec. 4.1 with the deduplication
+ * of the three-kernel insertion): successor counts and a scan place each
+ * group of 64 states' list region, the fused pass probes and places every
+ * successor and lists the ones whose candidates are all taken, then the
+ * evict and scrub kernels run on those lists.  Not for tables with
+ * HT_FLAG_SCRIPTED_HASH (HT_EINVAL).  Both modes give the same batch sizes,
+ * new counts and visited set; within a level the next frontier holds the same
+ * states (which copy of a repeated successor counts as new, and so its place,
+ * may differ).  Extra host array (may be NULL): level_ms[L] the device time of
+ * all of level L's kernels (split: count, scan, write, find-or-put, select;
+ * fused: the passes above, scans and the write), without the host round trips
+ * that read the level's sizes.  In fused mode fop_ms[L] is the time of the
+ * fused find-or-put passes.  Allocates its buffers; synchronises. */
 int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_t initial, uint32_t levels,
                       uint32_t mode, uint64_t* batch_sizes, uint64_t* new_counts, double* fop_ms,
                       double* level_ms, hipStream_t stream);

@@ -33,6 +33,7 @@
 #include <vector>
 
 #include "bucketed_dev.h"
+#include "cuckoo_dev.h"
 #include "runtime.h"
 
 using namespace ht;
@@ -144,6 +145,212 @@ __global__ __launch_bounds__(kBlock) void bfs_fused_write_kernel(BfsModelDev m, 
   }
 }
 
+// Successors of one state, one per call, in model order (the same order as
+// for_each_successor); lets a wave step through its lanes' successors
+// together, so wave-wide votes stay converged.
+struct SuccIter {
+  uint64_t st;
+  uint32_t p = 0, kk = 0, a = 0;
+  __device__ __forceinline__ bool next(const BfsModelDev& m, uint64_t& succ) {
+    while (p < 16) {
+      const uint32_t s = local_of(st, p);
+      if (kk < m.lcnt[p][s]) {
+        succ = (st & ~(15ull << (4 * p))) | ((uint64_t)m.ltgt[p][s][kk] << (4 * p));
+        ++kk;
+        return true;
+      }
+      ++p;
+      kk = 0;
+    }
+    while (a < 4) {
+      const uint32_t pp = m.sp[a], q = m.sq[a];
+      const int tp = m.pe[a][local_of(st, pp)], tq = m.qe[a][local_of(st, q)];
+      ++a;
+      if (tp >= 0 && tq >= 0) {
+        succ = (st & ~(15ull << (4 * pp)) & ~(15ull << (4 * q))) | ((uint64_t)tp << (4 * pp)) |
+               ((uint64_t)tq << (4 * q));
+        return true;
+      }
+    }
+    return false;
+  }
+};
+
+constexpr uint32_t kListed = 2;   // every candidate taken: listed for the evict pass
+
+// Probe and place of one key per lane (called by every lane of the wave; act
+// false for lanes without a key), as the single-table Cuckoo probe kernel
+// does it: h_1, h_2, ... are read in turn, the key found ends the search, an
+// empty candidate is compare-and-swapped at once (keys whose slot indices
+// coincide read all c first and then try the empty ones in order).  Returns
+// 1 placed, 0 found (or another copy placed it), kListed when every candidate
+// is taken.
+__device__ __forceinline__ uint32_t cuckoo_probe_key(const DevTable& t, uint64_t k, bool act, uint32_t sc,
+                                                     uint32_t oc) {
+  uint32_t res = 0;
+  bool pend = act && k != kEmpty;
+  if (act && k == kEmpty) res = sentinel_put(t);
+  if (pend && (sc | oc) && stash_query(t, k, sc, oc)) pend = false;
+  const bool dist = pend && hashes_distinct<false>(t, k);
+  uint32_t em = 0;
+  for (uint32_t j = 0; j < t.nhash && ballot(pend); ++j) {
+    uint64_t idx = 0, v = 0;
+    if (pend) {
+      idx = hidx<false>(t, k, j);
+      v = t.slots[idx];
+    }
+    bool cas = false;
+    if (pend) {
+      if (v == k) pend = false;
+      else if (v == kEmpty) {
+        if (dist) cas = true;
+        else em |= 1u << j;
+      }
+    }
+    if (cas) {
+      const uint64_t old = cas64(&t.slots[idx], kEmpty, k);
+      if (old == kEmpty) res = 1;
+      if (old == kEmpty || old == k) pend = false;
+    }
+  }
+  while (ballot(pend && em)) {
+    if (pend && em) {
+      const uint32_t j = (uint32_t)__builtin_ctz(em);
+      em &= em - 1;
+      const uint64_t old = cas64(&t.slots[hidx<false>(t, k, j)], kEmpty, k);
+      if (old == kEmpty) res = 1;
+      if (old == kEmpty || old == k) pend = false;
+    }
+  }
+  return pend ? kListed : res;
+}
+
+// Fused Cuckoo pass 1: a wave takes groups of 64 frontier states, one per
+// lane, and steps through their successors together; each successor is probed
+// and placed as above, new ones marked in the state's mask and counted, and
+// those with every candidate taken listed as (key, state << 7 | successor
+// number) in the group's region of the scratch list, which starts at the
+// group's first successor offset (a group never lists more keys than it has
+// successors).
+__global__ __launch_bounds__(kBlock) void bfs_cuckoo_probe_kernel(BfsModelDev m, DevTable t,
+                                                                  const uint64_t* __restrict__ f, uint64_t nf,
+                                                                  const unsigned long long* __restrict__ soff,
+                                                                  CuckooScratch s, uint32_t* __restrict__ gcnt,
+                                                                  unsigned long long* __restrict__ cnt,
+                                                                  uint64_t* __restrict__ mask) {
+  const int lane = lane_id();
+  const uint64_t wave =
+      __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  const uint64_t ngroups = (nf + kWave - 1) / kWave;
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  unsigned long long placed = 0;
+  for (uint64_t g = wave; g < ngroups; g += nwaves) {
+    const uint64_t i = g * kWave + lane;
+    const bool live = i < nf;
+    SuccIter it{live ? f[i] : 0ull};
+    const uint64_t begin = soff[g * kWave];
+    uint64_t m0 = 0, m1 = 0;
+    uint32_t k = 0, nnew = 0, nlist = 0;
+    for (;;) {
+      uint64_t succ = 0;
+      const bool has = live && it.next(m, succ);
+      if (!ballot(has)) break;
+      const uint32_t r = cuckoo_probe_key(t, succ, has, sc, oc);
+      if (has && r == 1) {
+        if (k < 64) m0 |= 1ull << k;
+        else m1 |= 1ull << (k - 64);
+        ++nnew;
+        ++placed;
+      }
+      const bool l = has && r == kListed;
+      const uint64_t mm = ballot(l);
+      if (l) {
+        const uint64_t slot = begin + nlist + lanes_below(mm);
+        s.wkey[slot] = succ;
+        s.wmeta[slot] = (i << 7) | k;
+      }
+      nlist += (uint32_t)__popcll(mm);
+      k += has ? 1u : 0u;
+    }
+    if (live) {
+      cnt[i] = nnew;
+      mask[2 * i] = m0;
+      mask[2 * i + 1] = m1;
+    }
+    if (lane == 0) gcnt[g] = nlist;
+  }
+  wave_count(t.ctr->size, placed, (uint32_t)wave);
+}
+
+// Fused Cuckoo pass 2: the listed keys, deduplicated in the scratch set; each
+// winner marks its successor new in the state's mask and count and runs the
+// eviction chain from h_1 (then the stash), as the single-table evict kernel
+// does.  The scratch-set slot a winner took replaces its list entry's meta.
+__global__ __launch_bounds__(kBlock) void bfs_cuckoo_evict_kernel(DevTable t, uint64_t nf,
+                                                                  const unsigned long long* __restrict__ soff,
+                                                                  CuckooScratch s, const uint32_t* __restrict__ gcnt,
+                                                                  unsigned long long* __restrict__ cnt,
+                                                                  uint64_t* __restrict__ mask) {
+  const int lane = lane_id();
+  const uint64_t wave =
+      __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  const uint64_t ngroups = (nf + kWave - 1) / kWave;
+  unsigned long long nnew = 0, nevict = 0;
+  for (uint64_t g = wave; g < ngroups; g += nwaves) {
+    const uint64_t begin = soff[g * kWave];
+    const uint32_t c = gcnt[g];
+    for (uint32_t e = lane; e < c; e += kWave) {
+      const uint64_t k = s.wkey[begin + e];
+      const uint64_t meta = s.wmeta[begin + e];
+      uint64_t p = mix64(k ^ s.dset_seed) & s.dset_mask;
+      bool winner = false;
+      for (;;) {
+        const uint64_t old = cas64(&s.dset[p], kEmpty, k);
+        if (old == kEmpty) {
+          winner = true;
+          break;
+        }
+        if (old == k) break;
+        p = (p + 1) & s.dset_mask;
+      }
+      s.wmeta[begin + e] = winner ? p : ~0ull;
+      if (!winner) continue;
+      const uint64_t i = meta >> 7;
+      const uint32_t kb = (uint32_t)(meta & 127);
+      __hip_atomic_fetch_or(&mask[2 * i + (kb >> 6)], 1ull << (kb & 63), __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&cnt[i], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      uint64_t y = k;
+      if (!cuckoo_chain<false>(t, y, hidx<false>(t, y, 0), nevict)) stash_put(t, y);
+      ++nnew;
+    }
+  }
+  wave_count(t.ctr->size, nnew, (uint32_t)wave);
+  wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
+}
+
+// Fused Cuckoo pass 3: empty the scratch-set slots the evict pass took.
+__global__ __launch_bounds__(kBlock) void bfs_cuckoo_scrub_kernel(uint64_t nf,
+                                                                  const unsigned long long* __restrict__ soff,
+                                                                  CuckooScratch s, const uint32_t* __restrict__ gcnt) {
+  const int lane = lane_id();
+  const uint64_t wave =
+      __builtin_amdgcn_readfirstlane((uint32_t)(((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  const uint64_t ngroups = (nf + kWave - 1) / kWave;
+  for (uint64_t g = wave; g < ngroups; g += nwaves) {
+    const uint64_t begin = soff[g * kWave];
+    const uint32_t c = gcnt[g];
+    for (uint32_t e = lane; e < c; e += kWave) {
+      const uint64_t p = s.wmeta[begin + e];
+      if (p != ~0ull) s.dset[p] = kEmpty;
+    }
+  }
+}
+
 // Device buffer that only grows.
 struct Buf {
   void* p = nullptr;
@@ -168,7 +375,7 @@ struct Buf {
 
 // Events of one exploration, destroyed on every return path.
 struct Events {
-  hipEvent_t e[6] = {};
+  hipEvent_t e[8] = {};
   ~Events() {
     for (auto& x : e)
       if (x) (void)hipEventDestroy(x);
@@ -192,7 +399,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
   if (t->cfg.key_words > 1) return fail(HT_EINVAL, "the exploration packs states into single-word keys");
   if (mode != HT_BFS_SPLIT && mode != HT_BFS_FUSED) return fail(HT_EINVAL, "unknown exploration mode");
   const bool fused = mode == HT_BFS_FUSED;
-  if (fused && t->cfg.kind != HT_BUCKETED) return fail(HT_EINVAL, "fused levels need a bucketed table");
+  const bool ck = fused && t->cfg.kind == HT_CUCKOO;   // fused Cuckoo levels: count and scan first
   if (fused && is_scripted(t)) return fail(HT_EINVAL, "fused levels do not take scripted-hash tables");
   BfsModelDev m;
   static_assert(sizeof(BfsModelDev) == sizeof(ht_bfs_model), "model layout");
@@ -202,7 +409,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
   for (int p = 0; p < 16; ++p)
     for (int q = 0; q < 16; ++q)
       if (m.lcnt[p][q] > 4) return fail(HT_EINVAL, "more than 4 local transitions");
-  Buf frontier, next, batch, flags, counts, offsets, tmp, nsel, masks;
+  Buf frontier, next, batch, flags, counts, offsets, tmp, nsel, masks, gcounts, noffsets;
   const uint32_t grid = max_blocks(t);
   rc = frontier.ensure(8);
   if (!rc) rc = nsel.ensure(16);
@@ -212,33 +419,38 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
   if (rc) return rc;
   const DevTable dt = launch_view(t);
   uint64_t nf = 1;
-  // ev[0..1]: first span of a level; ev[2..3]: second span (a host round trip
-  // between them reads sizes); ev[4]: end of the find-or-put (or fused pass);
-  // ev[5]: start of the find-or-put
+  // A level runs as up to three spans of device work with a host round trip
+  // between them (reading sizes, growing buffers): ev[0..1], ev[2..3],
+  // ev[4..5]; ev[6..7] bracket the find-or-put (or the fused passes).
   Events evs;
   hipEvent_t* ev = evs.e;
-  for (int i = 0; i < 6; ++i) HT_HIP(hipEventCreate(&ev[i]));
+  for (int i = 0; i < 8; ++i) HT_HIP(hipEventCreate(&ev[i]));
   for (uint32_t L = 0; L < levels && nf && rc == HT_OK; ++L) {
     rc = counts.ensure(nf * 8);
     if (!rc) rc = offsets.ensure(nf * 8);
     if (!rc && fused) rc = masks.ensure(nf * 16);
+    if (!rc && ck) rc = noffsets.ensure(nf * 8);
+    if (!rc && ck) rc = gcounts.ensure((nf + kWave - 1) / kWave * 4);
     if (rc) break;
     auto* cnt = static_cast<unsigned long long*>(counts.p);
     auto* off = static_cast<unsigned long long*>(offsets.p);
     auto* fr = static_cast<const uint64_t*>(frontier.p);
     auto* ns = static_cast<unsigned long long*>(nsel.p);
+    auto* mk = static_cast<uint64_t*>(masks.p);
     const uint32_t g1 = (uint32_t)std::min<uint64_t>((nf + kBlock - 1) / kBlock, grid);
     size_t tb = 0;
     HT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)nf, s));
     rc = tmp.ensure(std::max<size_t>(tb, 256));
     if (rc) break;
-    if (fused) HT_HIP(hipMemsetAsync(ns, 0, 8, s));
+    if (fused && !ck) HT_HIP(hipMemsetAsync(ns, 0, 8, s));
+    double lms = 0.0;
+    // span 1: successor counts (split, fused Cuckoo) or the fused bucketed pass, then a scan
     HT_HIP(hipEventRecord(ev[0], s));
-    if (fused) {
-      hipLaunchKernelGGL(bfs_fused_kernel, dim3(g1), dim3(kBlock), 0, s, m, dt, fr, nf, cnt,
-                         static_cast<uint64_t*>(masks.p), ns);
+    if (fused && !ck) {
+      HT_HIP(hipEventRecord(ev[6], s));
+      hipLaunchKernelGGL(bfs_fused_kernel, dim3(g1), dim3(kBlock), 0, s, m, dt, fr, nf, cnt, mk, ns);
       HT_HIP(hipGetLastError());
-      HT_HIP(hipEventRecord(ev[4], s));
+      HT_HIP(hipEventRecord(ev[7], s));
     } else {
       hipLaunchKernelGGL(bfs_count_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, cnt);
       HT_HIP(hipGetLastError());
@@ -248,28 +460,64 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
     unsigned long long last[3] = {0, 0, 0};
     HT_HIP(hipMemcpyAsync(&last[0], off + nf - 1, 8, hipMemcpyDeviceToHost, s));
     HT_HIP(hipMemcpyAsync(&last[1], cnt + nf - 1, 8, hipMemcpyDeviceToHost, s));
-    if (fused) HT_HIP(hipMemcpyAsync(&last[2], ns, 8, hipMemcpyDeviceToHost, s));
+    if (fused && !ck) HT_HIP(hipMemcpyAsync(&last[2], ns, 8, hipMemcpyDeviceToHost, s));
     HT_HIP(hipStreamSynchronize(s));
-    const uint64_t total = last[0] + last[1];   // split: successors; fused: new states
-    const uint64_t nb = fused ? last[2] : total;
+    lms += span_ms(ev[0], ev[1]);
+    const uint64_t total = last[0] + last[1];   // fused bucketed: new states; otherwise successors
+    const uint64_t nb = (fused && !ck) ? last[2] : total;
     if (batch_sizes) batch_sizes[L] = nb;
-    if ((fused ? total : nb) >= (1ull << 31)) {   // the next scan counts in int
-      rc = fail(HT_EINVAL, fused ? "a level's new states exceed 2^31" : "a level's batch exceeds 2^31 keys");
-      break;
-    }
     uint64_t nnew = 0;
-    if (fused) {
+    if (fused && !ck) {
       nnew = total;
+    } else if (ck) {
+      // span 2: fused probe and placement, evict, scrub, scan of the new counts
+      rc = reserve_scratch(t, nb);   // lists and scratch set for this level, outside the timed spans
+      if (rc) break;
+      const CuckooScratch sc = scratch_view(t, nb);
+      auto* gc = static_cast<uint32_t*>(gcounts.p);
+      auto* noff = static_cast<unsigned long long*>(noffsets.p);
+      const uint64_t ngroups = (nf + kWave - 1) / kWave;
+      const uint32_t g2 = (uint32_t)std::min<uint64_t>((ngroups + 3) / 4, grid);
+      HT_HIP(hipEventRecord(ev[2], s));
+      HT_HIP(hipEventRecord(ev[6], s));
+      hipLaunchKernelGGL(bfs_cuckoo_probe_kernel, dim3(g2), dim3(kBlock), 0, s, m, dt, fr, nf, off, sc, gc, cnt, mk);
+      HT_HIP(hipGetLastError());
+      hipLaunchKernelGGL(bfs_cuckoo_evict_kernel, dim3(g2), dim3(kBlock), 0, s, dt, nf, off, sc, gc, cnt, mk);
+      HT_HIP(hipGetLastError());
+      hipLaunchKernelGGL(bfs_cuckoo_scrub_kernel, dim3(g2), dim3(kBlock), 0, s, nf, off, sc, gc);
+      HT_HIP(hipGetLastError());
+      HT_HIP(hipEventRecord(ev[7], s));
+      HT_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, cnt, noff, (int)nf, s));
+      HT_HIP(hipEventRecord(ev[3], s));
+      unsigned long long lastn[2] = {0, 0};
+      HT_HIP(hipMemcpyAsync(&lastn[0], noff + nf - 1, 8, hipMemcpyDeviceToHost, s));
+      HT_HIP(hipMemcpyAsync(&lastn[1], cnt + nf - 1, 8, hipMemcpyDeviceToHost, s));
+      HT_HIP(hipStreamSynchronize(s));
+      lms += span_ms(ev[2], ev[3]);
+      nnew = lastn[0] + lastn[1];
+    }
+    if (fused) {
+      if (nnew >= (1ull << 31)) {   // the next level's scans count in int
+        rc = fail(HT_EINVAL, "a level's new states exceed 2^31");
+        break;
+      }
+      // last span: the new states written at their scanned offsets
       rc = next.ensure(std::max<uint64_t>(nnew, 1) * 8);
       if (rc) break;
-      HT_HIP(hipEventRecord(ev[2], s));
-      hipLaunchKernelGGL(bfs_fused_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf,
-                         static_cast<const uint64_t*>(masks.p), off, static_cast<uint64_t*>(next.p));
+      const unsigned long long* woff = ck ? static_cast<const unsigned long long*>(noffsets.p) : off;
+      HT_HIP(hipEventRecord(ev[4], s));
+      hipLaunchKernelGGL(bfs_fused_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, mk, woff,
+                         static_cast<uint64_t*>(next.p));
       HT_HIP(hipGetLastError());
-      HT_HIP(hipEventRecord(ev[3], s));
+      HT_HIP(hipEventRecord(ev[5], s));
       HT_HIP(hipStreamSynchronize(s));
-      if (fop_ms) fop_ms[L] = span_ms(ev[0], ev[4]);
+      lms += span_ms(ev[4], ev[5]);
+      if (fop_ms) fop_ms[L] = span_ms(ev[6], ev[7]);
     } else {
+      if (nb >= (1ull << 31)) {
+        rc = fail(HT_EINVAL, "a level's batch exceeds 2^31 keys");
+        break;
+      }
       rc = batch.ensure(std::max<uint64_t>(nb, 1) * 8);
       if (!rc) rc = flags.ensure(std::max<uint64_t>(nb, 1));
       if (!rc) rc = next.ensure(std::max<uint64_t>(nb, 1) * 8);
@@ -281,22 +529,24 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       HT_HIP(hipcub::DeviceSelect::Flagged(nullptr, tbs, bt, fl, static_cast<uint64_t*>(next.p), ns, (int)nb, s));
       rc = tmp.ensure(std::max<size_t>(tbs, 256));
       if (rc) break;
+      // span 2: write the batch, find-or-put it, select the new keys
       HT_HIP(hipEventRecord(ev[2], s));
       hipLaunchKernelGGL(bfs_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, off, bt);
       HT_HIP(hipGetLastError());
-      HT_HIP(hipEventRecord(ev[5], s));
+      HT_HIP(hipEventRecord(ev[6], s));
       rc = do_find_or_put(t, bt, nb, fl, s);
       if (rc) break;
-      HT_HIP(hipEventRecord(ev[4], s));
+      HT_HIP(hipEventRecord(ev[7], s));
       HT_HIP(hipcub::DeviceSelect::Flagged(tmp.p, tbs, bt, fl, static_cast<uint64_t*>(next.p), ns, (int)nb, s));
       HT_HIP(hipEventRecord(ev[3], s));
       unsigned long long nsv = 0;
       HT_HIP(hipMemcpyAsync(&nsv, ns, 8, hipMemcpyDeviceToHost, s));
       HT_HIP(hipStreamSynchronize(s));
+      lms += span_ms(ev[2], ev[3]);
       nnew = nsv;
-      if (fop_ms) fop_ms[L] = span_ms(ev[5], ev[4]);
+      if (fop_ms) fop_ms[L] = span_ms(ev[6], ev[7]);
     }
-    if (level_ms) level_ms[L] = span_ms(ev[0], ev[1]) + span_ms(ev[2], ev[3]);
+    if (level_ms) level_ms[L] = lms;
     if (new_counts) new_counts[L] = nnew;
     std::swap(frontier.p, next.p);
     std::swap(frontier.bytes, next.bytes);

@@ -69,8 +69,11 @@ def test_bfs_full_size_seed2():
         assert v[5] == g["visited_after_level5"] and v[6] == g["visited_after_level6"]
 
 
-FUSED = [dict(bucket_slots=8), dict(bucket_slots=16), dict(bucket_slots=64, nhash=2),
-         dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)]
+FUSED = [("bucketed", dict(bucket_slots=8)), ("bucketed", dict(bucket_slots=16)),
+         ("bucketed", dict(bucket_slots=64, nhash=2)),
+         ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)),
+         ("cuckoo", dict()), ("cuckoo", dict(nhash=4)), ("cuckoo", dict(nhash=2)),
+         ("cuckoo", dict(flags=b.HT_FLAG_CUCKOO_PAPER_ORDER))]
 
 
 def oracle_bfs(model, initial, levels):
@@ -86,15 +89,15 @@ def oracle_bfs(model, initial, levels):
     return o, sizes, news
 
 
-@pytest.mark.parametrize("kw", FUSED)
-def test_bfs_fused_levels_match_oracle(kw):
-    """Fused levels (generation and find-or-put in one kernel) give the
-    oracle's batch sizes, new counts and visited set."""
+@pytest.mark.parametrize("kind,kw", FUSED)
+def test_bfs_fused_levels_match_oracle(kind, kw):
+    """Fused levels (successor generation joined with the find-or-put) give
+    the oracle's batch sizes, new counts and visited set."""
     model = inputs.BfsModel(1)
     o, sizes, news = oracle_bfs(model, 0, 5)
     kw = dict(kw)
     kw.setdefault("nhash", 3)
-    with b.Table("bucketed", capacity=int(np.ceil(o.size / 0.7)), **kw) as t:
+    with b.Table(kind, capacity=int(np.ceil(o.size / 0.7)), **kw) as t:
         r = t.bfs_explore(model, 5, fused=True)
         assert r["batch_sizes"] == sizes
         assert r["new_counts"] == news
@@ -103,14 +106,15 @@ def test_bfs_fused_levels_match_oracle(kw):
         assert t.size() == o.size
 
 
-def test_bfs_fused_from_all_ones_state():
+@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+def test_bfs_fused_from_all_ones_state(kind, kw):
     """The all-ones state (the table's empty marker) as the initial state:
     fused and split levels agree with the oracle."""
     model = inputs.BfsModel(2)
     init = int(b.EMPTY)
     o, sizes, news = oracle_bfs(model, init, 4)
     for fused in (False, True):
-        with b.Table("bucketed", capacity=int(np.ceil(o.size / 0.7)), nhash=3, bucket_slots=8) as t:
+        with b.Table(kind, capacity=int(np.ceil(o.size / 0.7)), nhash=3, **kw) as t:
             r = t.bfs_explore(model, 4, initial=init, fused=fused)
             assert r["batch_sizes"] == sizes, fused
             assert r["new_counts"] == news, fused
@@ -118,10 +122,11 @@ def test_bfs_fused_from_all_ones_state():
             assert t.query(torch.tensor([-1], dtype=torch.int64, device="cuda")).item() == 1
 
 
-def test_bfs_fused_full_size_seed1():
+@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+def test_bfs_fused_full_size_seed1(kind, kw):
     g = golden()["seed1"]
     visited = g["visited_after"]
-    with b.Table("bucketed", capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, bucket_slots=8) as t:
+    with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, **kw) as t:
         r = t.bfs_explore(inputs.BfsModel(1), 7, fused=True)
         assert r["batch_sizes"] == g["batch_sizes"]
         assert list(1 + np.cumsum(r["new_counts"])) == visited
@@ -142,8 +147,8 @@ def test_bfs_split_level_times():
 
 def test_bfs_fused_rejects_other_tables():
     model = inputs.BfsModel(1)
-    for kw in (dict(kind="cuckoo"), dict(kind="bucketed", flags=b.HT_FLAG_SCRIPTED_HASH)):
-        with b.Table(capacity=1024, **kw) as t:
+    for kind in ("bucketed", "cuckoo"):
+        with b.Table(kind, capacity=1024, flags=b.HT_FLAG_SCRIPTED_HASH) as t:
             with pytest.raises(b.HtError):
                 t.bfs_explore(model, 2, fused=True)
     with b.Table("bucketed", capacity=1024) as t:

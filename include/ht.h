@@ -363,7 +363,7 @@ enum {
 typedef struct {
   uint32_t op;              /* HT_OP_FIND_OR_PUT or HT_OP_QUERY */
   uint32_t table;           /* index into the server's tables */
-  const uint64_t* h_keys;
+  const uint64_t* h_keys;   /* n keys; on a table with key_words > 1, n rows of key_words words */
   uint64_t n;
   uint8_t* h_out;           /* n flags: as ht_find_or_put / ht_query */
   double arrival_s;

@@ -672,16 +672,21 @@ class Server:
         for i, (op, table, keys, arrival) in enumerate(reqs):
             if keys.device.type != "cpu" or not keys.is_pinned():
                 raise ValueError("request keys must be a pinned host tensor")
+            # an index the server does not hold is rejected by the library
+            w = self.tables[int(table)].key_words if 0 <= int(table) < len(self.tables) else 1
+            if keys.numel() % w:
+                raise ValueError(f"request {i}: keys are not whole rows of {w} words")
+            nk = keys.numel() // w
             o = outs[i]
             if o is None:
-                o = torch.empty(keys.numel(), dtype=torch.uint8, pin_memory=True)
+                o = torch.empty(nk, dtype=torch.uint8, pin_memory=True)
             keep.append(keys)
             res.append(o)
             arr[i].op = HT_OP_QUERY if op == "query" else HT_OP_FIND_OR_PUT
             arr[i].table = int(table)
-            arr[i].h_keys = keys.data_ptr() if keys.numel() else None
-            arr[i].n = keys.numel()
-            arr[i].h_out = o.data_ptr() if keys.numel() else None
+            arr[i].h_keys = keys.data_ptr() if nk else None
+            arr[i].n = nk
+            arr[i].h_out = o.data_ptr() if nk else None
             arr[i].arrival_s = float(arrival)
         st = HtServerStats()
         _check(load().ht_server_run(self.handle, arr, n, C.byref(st)), "ht_server_run")

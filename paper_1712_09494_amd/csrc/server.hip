@@ -21,6 +21,8 @@
 //     its queries as one many-table query launch (a query large enough to
 //     fill the device alone gets its own launch), all on the group's stream
 //     between the host-to-device copies and the device-to-host copies;
+//     requests on state-vector tables run their tables' own kernels inside
+//     the group (the many-table launches take single-word keys);
 //   - overlap: groups on different stream slots run concurrently.
 // The sequential baseline runs one request at a time, waiting for each.
 #include <algorithm>
@@ -100,7 +102,10 @@ class StagingPool {
   std::vector<std::pair<uint64_t, uint64_t>> free_;
 };
 
-uint64_t stage_bytes(uint64_t n) { return (n * 8 + 255) / 256 * 256 + (n + 255) / 256 * 256; }
+// Staging of one request: its keys (w words each) and its flags, each in
+// 256-byte pieces (so vector keys keep the 16-byte alignment they need).
+uint64_t key_bytes(uint64_t n, uint32_t w) { return (n * 8 * w + 255) / 256 * 256; }
+uint64_t stage_bytes(uint64_t n, uint32_t w) { return key_bytes(n, w) + (n + 255) / 256 * 256; }
 
 }  // namespace
 
@@ -138,7 +143,6 @@ int ht_server_create(ht_table* const* tables, uint32_t ntables, const ht_server_
     int rc = check_table(tables[i]);
     if (rc) return rc;
     if (is_scripted(tables[i])) return fail(HT_EINVAL, "scripted-hash tables cannot be served");
-    if (tables[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables cannot be served");
   }
   ht_server_config c;
   ht_server_config_default(&c);
@@ -204,8 +208,10 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
     if (r.table >= nt) return fail(HT_EINVAL, "request names a table the server does not hold");
     if (r.op != HT_OP_FIND_OR_PUT && r.op != HT_OP_QUERY) return fail(HT_EINVAL, "bad request op");
     if (r.n && (!r.h_keys || !r.h_out)) return fail(HT_EINVAL, "request with NULL keys or flags");
+    if (s->tables[r.table]->cfg.key_words > 1 && r.n >= (1ull << (kArenaBits - 1)))
+      return fail(HT_EINVAL, "vector request of 2^33 keys or more");
     max_n = std::max(max_n, r.n);
-    max_stage = std::max(max_stage, stage_bytes(r.n));
+    max_stage = std::max(max_stage, stage_bytes(r.n, s->tables[r.table]->cfg.key_words));
     total_keys += r.n;
     if (r.op == HT_OP_FIND_OR_PUT) need[r.table] = std::max(need[r.table], r.n);
   }
@@ -223,7 +229,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
   }
   // everything that allocates happens before the clock starts
   for (uint32_t t = 0; t < nt; ++t)
-    if (s->tables[t]->cfg.kind == HT_CUCKOO && need[t]) {
+    if ((s->tables[t]->cfg.kind == HT_CUCKOO || s->tables[t]->cfg.key_words > 1) && need[t]) {
       int rc = reserve_scratch(s->tables[t], need[t]);
       if (rc) return rc;
     }
@@ -279,7 +285,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
         ht_request& r = reqs[sl.reqs[k]];
         r.done_s = now;
         busy[r.table] = 0;
-        if (r.n) s->pool.free(sl.offs[k], stage_bytes(r.n));
+        if (r.n) s->pool.free(sl.offs[k], stage_bytes(r.n, s->tables[r.table]->cfg.key_words));
         ++completed;
       }
       sl.reqs.clear();
@@ -310,7 +316,7 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
           ++it;
           continue;
         }
-        const uint64_t sb = stage_bytes(reqs[idx].n);
+        const uint64_t sb = stage_bytes(reqs[idx].n, s->tables[t]->cfg.key_words);
         const uint64_t off = sb ? s->pool.alloc(sb) : 0;
         if (off == ~0ull) {
           ++throttled;
@@ -338,7 +344,8 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
         const ht_request& r = reqs[sl.reqs[k]];
         if (!r.n) continue;
         uint64_t* dk = reinterpret_cast<uint64_t*>(s->pool.ptr(sl.offs[k]));
-        hipError_t e = hipMemcpyAsync(dk, r.h_keys, r.n * 8, hipMemcpyHostToDevice, st);
+        hipError_t e = hipMemcpyAsync(dk, r.h_keys, r.n * 8 * s->tables[r.table]->cfg.key_words,
+                                      hipMemcpyHostToDevice, st);
         if (e != hipSuccess) err = hip_fail(e, "serving key copy");
       }
       for (size_t k = 0; k < sl.reqs.size() && err == HT_OK; ++k) {
@@ -346,8 +353,12 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
         if (!r.n) continue;
         ht_table* tb = s->tables[r.table];
         uint64_t* dk = reinterpret_cast<uint64_t*>(s->pool.ptr(sl.offs[k]));
-        uint8_t* dflag = reinterpret_cast<uint8_t*>(s->pool.ptr(sl.offs[k]) + (r.n * 8 + 255) / 256 * 256);
-        if (r.op == HT_OP_FIND_OR_PUT && tb->cfg.kind == HT_BUCKETED && s->cfg.merge > 1) {
+        uint8_t* dflag =
+            reinterpret_cast<uint8_t*>(s->pool.ptr(sl.offs[k]) + key_bytes(r.n, s->tables[r.table]->cfg.key_words));
+        if (tb->cfg.key_words > 1) {
+          // vector tables: their own kernels (the many-table launches take single-word keys)
+          err = r.op == HT_OP_FIND_OR_PUT ? do_find_or_put(tb, dk, r.n, dflag, st) : do_query(tb, dk, r.n, dflag, st);
+        } else if (r.op == HT_OP_FIND_OR_PUT && tb->cfg.kind == HT_BUCKETED && s->cfg.merge > 1) {
           specs.push_back(MultiSpec{launch_view(tb), dk, dflag, r.n});
         } else if (r.op == HT_OP_FIND_OR_PUT && s->cfg.merge > 1) {
           MultiCuckooSpec cs{};
@@ -378,7 +389,8 @@ int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats
       for (size_t k = 0; k < sl.reqs.size() && err == HT_OK; ++k) {
         const ht_request& r = reqs[sl.reqs[k]];
         if (!r.n) continue;
-        uint8_t* dflag = reinterpret_cast<uint8_t*>(s->pool.ptr(sl.offs[k]) + (r.n * 8 + 255) / 256 * 256);
+        uint8_t* dflag =
+            reinterpret_cast<uint8_t*>(s->pool.ptr(sl.offs[k]) + key_bytes(r.n, s->tables[r.table]->cfg.key_words));
         hipError_t e = hipMemcpyAsync(r.h_out, dflag, r.n, hipMemcpyDeviceToHost, st);
         if (e != hipSuccess) err = hip_fail(e, "serving flag copy");
       }

@@ -116,3 +116,53 @@ def test_served_rejects_bad_requests():
         srv.run([("fop", 0, torch.zeros(4, dtype=torch.int64), 0.0)])   # not pinned
     srv.close()
     t.close()
+
+
+def _rows(a, w):
+    a = np.ascontiguousarray(a).view(np.uint64).reshape(-1, w)
+    return a.view(np.dtype((np.void, 8 * w))).reshape(-1)
+
+
+def test_served_vector_tables_beside_single_word_ones():
+    """State-vector tables (2 and 4 words, both designs) served beside
+    single-word tables in merged groups: every request's result equals the
+    oracle's in arrival order, and every table's stored set equals the
+    oracle's."""
+    from oracle import VecOracle
+    specs = [("bucketed", dict(bucket_slots=8), 1), ("cuckoo", {}, 2), ("bucketed", dict(bucket_slots=16), 4),
+             ("cuckoo", {}, 4), ("bucketed", dict(bucket_slots=8), 2), ("cuckoo", {}, 1)]
+    tables = [b.Table(k, capacity=1 << 14, key_words=w, **kw) for k, kw, w in specs]
+    rng = np.random.default_rng(21)
+    pools = [inputs.vector_of_index(np.arange(6000), w, seed=40 + i, structured=bool(i % 2)) if w > 1
+             else inputs.uniform_keys(6000, seed=40 + i) for i, (_, _, w) in enumerate(specs)]
+    reqs = []
+    for _ in range(150):
+        t = int(rng.integers(0, len(specs)))
+        keys = pools[t][rng.integers(0, len(pools[t]), int(rng.integers(0, 700)))]
+        reqs.append(("query" if rng.random() < 0.4 else "fop", t, keys, 0.0))
+    srv = b.Server(tables, slots=4, merge=8)
+    outs, _, _, _, st = srv.run([(op, t, pinned(k), a) for op, t, k, a in reqs])
+    assert st["merged_launches"] > 0
+    oras = [VecOracle(w) if w > 1 else Oracle() for _, _, w in specs]
+    for i, (op, t, keys, _) in enumerate(reqs):          # released together: arrival order is index order
+        w = specs[t][2]
+        got = outs[i].numpy()
+        assert got.size == len(keys)
+        if op == "query":
+            check_query_r1(got, oras[t].query(keys), f"req {i}")
+        elif w == 1:
+            check_flags_r2(keys, got, oras[t].find_or_put(keys), f"req {i}")
+        else:
+            exp = oras[t].find_or_put(keys)
+            assert set(np.unique(got).tolist()) <= {0, 1}, f"req {i}"
+            v = _rows(keys, w)
+            assert np.array_equal(np.sort(v[got == 1]), np.sort(v[exp == 1])), f"req {i}"
+    for t, (_, _, w) in enumerate(specs):
+        d = tables[t].dump().cpu().numpy()
+        if w == 1:
+            assert np.array_equal(np.sort(d.view(np.uint64)), oras[t].dump())
+        else:
+            assert np.array_equal(np.sort(_rows(d, w)), np.sort(_rows(oras[t].dump(), w)))
+    srv.close()
+    for t in tables:
+        t.close()

@@ -194,11 +194,13 @@ int ht_query(ht_table* t, const uint64_t* d_keys, uint64_t n,
  * kernel of Sec. 5, applied to many tables).  t[i], d_keys[i], n[i],
  * d_out_is_new[i] are host arrays of per-table arguments (the key and flag
  * pointers themselves are device pointers; a flag pointer may be NULL).
- * Tables may mix kinds, bucket sizes and hash counts; each table may appear
- * at most once; scripted-hash tables are rejected.  All bucketed tables are
- * served by one persistent kernel; all Cuckoo tables then run their three
- * phases (probe and place, evict, scrub) as three launches over all of them,
- * on the same stream.  Results equal one ht_find_or_put per table.
+ * Tables may mix kinds, bucket sizes, hash counts and key widths; each table
+ * may appear at most once; scripted-hash tables are rejected.  All bucketed
+ * tables of single-word keys are served by one persistent kernel; all Cuckoo
+ * tables of single-word keys then run their three phases (probe and place,
+ * evict, scrub) as three launches over all of them; state-vector tables
+ * (key_words > 1: n[i] rows, 16-byte aligned) then run their own kernels,
+ * all on the same stream.  Results equal one ht_find_or_put per table.
  * Builds a plan (allocating), launches it and synchronises `stream`. */
 int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
@@ -208,10 +210,11 @@ int ht_find_or_put_multi(ht_table* const* t, const uint64_t* const* d_keys,
  * to many tables): d_out_found[i][j] = 1 if d_keys[i][j] is a member of
  * t[i], else 0.  Arguments as for ht_find_or_put_multi (host arrays of
  * device pointers); flag pointers must not be NULL where n[i] > 0.  Tables
- * may mix kinds and repeat; scripted-hash and vector tables are rejected.
- * Batches too small to fill the device alone share one kernel (bucketed
- * tables read by lane groups, Cuckoo tables by one lane per key); a batch
- * that fills it alone runs the single-table query.  Results equal one
+ * may mix kinds and repeat; scripted-hash tables are rejected.  Batches of
+ * single-word keys too small to fill the device alone share one kernel
+ * (bucketed tables read by lane groups, Cuckoo tables by one lane per key);
+ * a batch that fills it alone, and every state-vector table (n[i] rows,
+ * 16-byte aligned), runs the single-table query.  Results equal one
  * ht_query per table.  Allocates the descriptors and synchronises `stream`. */
 int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys,
                    const uint64_t* n, uint8_t* const* d_out_found,
@@ -219,16 +222,18 @@ int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys,
 
 typedef struct ht_multi_plan ht_multi_plan;
 
-/* Prepare a many-table find-or-put: validates the arguments, reserves each
- * Cuckoo table's scratch for its batch, and copies the tables' descriptors
- * and work-item lists to the device (allocates, synchronises).  The
- * key and flag buffers must stay valid for every launch of the plan. */
+/* Prepare a many-table find-or-put: validates the arguments (as
+ * ht_find_or_put_multi), reserves each Cuckoo and state-vector table's
+ * scratch for its batch, and copies the tables' descriptors and work-item
+ * lists to the device (allocates, synchronises).  The key and flag buffers
+ * must stay valid for every launch of the plan. */
 int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
                          uint32_t ntables, ht_multi_plan** out);
 
 /* Run the plan on `stream`: one persistent kernel for the bucketed tables,
- * then three phase kernels covering every Cuckoo table.
+ * then three phase kernels covering every Cuckoo table, then each
+ * state-vector table's own kernels.
  * Allocates nothing, uses no memset and does not synchronise, so it may be
  * captured in a HIP graph and replayed.  Launches of one plan, and calls on
  * its tables, must be ordered on one stream. */

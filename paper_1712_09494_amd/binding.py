@@ -359,31 +359,32 @@ def ht_query(h: int, keys, out=None, stream=None, key_words: int = 1):
     return o
 
 
-def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=None):
+def _multi_args(handles, keys_list, outs, key_words):
+    """Marshal per-table arguments: keys as n rows of key_words[i] words."""
     n = len(handles)
     ks = [_key_tensor(k) for k in keys_list]
     if len(ks) != n:
         raise ValueError("one key tensor per table")
-    os_ = [_out_tensor(None if outs is None else outs[i], ks[i].numel(), ks[i]) for i in range(n)]
+    ws = [1] * n if key_words is None else [int(w) for w in key_words]
+    counts = [_count(ks[i], ws[i]) for i in range(n)]
+    os_ = [_out_tensor(None if outs is None else outs[i], counts[i], ks[i]) for i in range(n)]
     th = (_vp * n)(*handles)
     kp = (_vp * n)(*[k.data_ptr() for k in ks])
-    nn = (_u64 * n)(*[k.numel() for k in ks])
+    nn = (_u64 * n)(*counts)
     op = (_vp * n)(*[o.data_ptr() for o in os_])
-    _check(load().ht_find_or_put_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_find_or_put_multi")
+    return ks, os_, th, kp, nn, op
+
+
+def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=None, key_words=None):
+    ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
+    _check(load().ht_find_or_put_multi(th, kp, nn, op, len(handles), _stream_handle(stream)),
+           "ht_find_or_put_multi")
     return os_
 
 
-def ht_query_multi(handles: Sequence[int], keys_list, outs=None, stream=None):
-    n = len(handles)
-    ks = [_key_tensor(k) for k in keys_list]
-    if len(ks) != n:
-        raise ValueError("one key tensor per table")
-    os_ = [_out_tensor(None if outs is None else outs[i], ks[i].numel(), ks[i]) for i in range(n)]
-    th = (_vp * n)(*handles)
-    kp = (_vp * n)(*[k.data_ptr() for k in ks])
-    nn = (_u64 * n)(*[k.numel() for k in ks])
-    op = (_vp * n)(*[o.data_ptr() for o in os_])
-    _check(load().ht_query_multi(th, kp, nn, op, n, _stream_handle(stream)), "ht_query_multi")
+def ht_query_multi(handles: Sequence[int], keys_list, outs=None, stream=None, key_words=None):
+    ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
+    _check(load().ht_query_multi(th, kp, nn, op, len(handles), _stream_handle(stream)), "ht_query_multi")
     return os_
 
 
@@ -395,15 +396,8 @@ class MultiPlan:
     def __init__(self, tables, keys_list, outs=None):
         n = len(tables)
         self.tables = list(tables)
-        self.keys = [_key_tensor(k) for k in keys_list]
-        if len(self.keys) != n:
-            raise ValueError("one key tensor per table")
-        self.outs = [_out_tensor(None if outs is None else outs[i], self.keys[i].numel(), self.keys[i])
-                     for i in range(n)]
-        th = (_vp * n)(*[t.handle for t in self.tables])
-        kp = (_vp * n)(*[k.data_ptr() for k in self.keys])
-        nn = (_u64 * n)(*[k.numel() for k in self.keys])
-        op = (_vp * n)(*[o.data_ptr() for o in self.outs])
+        self.keys, self.outs, th, kp, nn, op = _multi_args([t.handle for t in self.tables], keys_list, outs,
+                                                           [t.key_words for t in self.tables])
         h = _vp()
         _check(load().ht_multi_plan_create(th, kp, nn, op, n, C.byref(h)), "ht_multi_plan_create")
         self.handle = h.value
@@ -708,11 +702,13 @@ class Server:
 
 
 def find_or_put_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):
-    return ht_find_or_put_multi([t.handle for t in tables], keys_list, outs, stream)
+    tables = list(tables)
+    return ht_find_or_put_multi([t.handle for t in tables], keys_list, outs, stream, [t.key_words for t in tables])
 
 
 def query_multi(tables: Iterable[Table], keys_list, outs=None, stream=None):
-    return ht_query_multi([t.handle for t in tables], keys_list, outs, stream)
+    tables = list(tables)
+    return ht_query_multi([t.handle for t in tables], keys_list, outs, stream, [t.key_words for t in tables])
 
 
 def u64(t) -> np.ndarray:

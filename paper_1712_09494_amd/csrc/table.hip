@@ -148,8 +148,15 @@ void resolve_timings() {
 
 
 struct ht_multi_plan {
+  struct VecJob {             // a state-vector table: its own kernels, after the merged launches
+    ht_table* t;
+    const uint64_t* keys;
+    uint64_t n;
+    uint8_t* out;
+  };
   std::vector<ht_table*> tables;
   MultiPlanDev dev;           // bucketed persistent launch + Cuckoo phase launches
+  std::vector<VecJob> vec;
   uint32_t grid = 0;
 };
 
@@ -644,6 +651,7 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
   if (ntables > (1u << 23)) return fail(HT_EINVAL, "too many tables in one plan");
   std::vector<MultiSpec> specs;
   std::vector<MultiCuckooSpec> cuckoo;
+  std::vector<ht_multi_plan::VecJob> vec;
   std::vector<ht_table*> seen;
   for (uint32_t i = 0; i < ntables; ++i) {
     int rc = check_table(t[i]);
@@ -654,7 +662,15 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
     if (n[i] && !d_keys[i]) return fail(HT_EINVAL, "keys is NULL");
     if (n[i] >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
     if (is_scripted(t[i])) return fail(HT_EINVAL, "scripted-hash tables are not supported by the multi-table call");
-    if (t[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables are not supported by the multi-table call");
+    if (t[i]->cfg.key_words > 1) {
+      if (n[i] && (reinterpret_cast<uintptr_t>(d_keys[i]) & 15))
+        return fail(HT_EINVAL, "vector keys must be 16-byte aligned");
+      if (n[i] >= (1ull << (kArenaBits - 1))) return fail(HT_EINVAL, "vector batch of 2^33 keys or more");
+      rc = reserve_scratch(t[i], n[i]);     // so that launches allocate nothing
+      if (rc) return rc;
+      if (n[i]) vec.push_back(ht_multi_plan::VecJob{t[i], d_keys[i], n[i], d_out_is_new[i]});
+      continue;
+    }
     if (t[i]->cfg.kind == HT_CUCKOO) {
       rc = reserve_scratch(t[i], n[i]);     // so that launches allocate nothing
       if (rc) return rc;
@@ -680,6 +696,7 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys, cons
   }
   ht_multi_plan* p = new ht_multi_plan();
   p->tables = seen;
+  p->vec = vec;
   int dev = 0;
   (void)hipGetDevice(&dev);
   p->grid = device_cus(dev) * 8;
@@ -705,6 +722,11 @@ int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t s) {
       KernelTimer kt(names[ph], s);
       HT_HIP(multi_cuckoo_launch(p->dev, ph, s));
     }
+  }
+  // vector tables: scratch reserved at creation, so these only launch kernels
+  for (const auto& j : p->vec) {
+    int rc = do_find_or_put(j.t, j.keys, j.n, j.out, s);
+    if (rc) return rc;
   }
   return HT_OK;
 }
@@ -747,7 +769,8 @@ int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint
     if (n[i] && (!d_keys[i] || !d_out_found[i])) return fail(HT_EINVAL, "keys or flags is NULL");
     if (n[i] >= (1ull << 40)) return fail(HT_EINVAL, "batch above 2^40 keys");
     if (is_scripted(t[i])) return fail(HT_EINVAL, "scripted-hash tables are not supported by the multi-table call");
-    if (t[i]->cfg.key_words > 1) return fail(HT_EINVAL, "vector tables are not supported by the multi-table call");
+    if (t[i]->cfg.key_words > 1 && n[i] && (reinterpret_cast<uintptr_t>(d_keys[i]) & 15))
+      return fail(HT_EINVAL, "vector keys must be 16-byte aligned");
   }
   int dev = 0;
   (void)hipGetDevice(&dev);
@@ -760,7 +783,7 @@ int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys, const uint
     q.out = d_out_found[i];
     q.n = n[i];
     q.cuckoo = t[i]->cfg.kind == HT_CUCKOO;
-    if (multi_query_alone(q, grid)) {
+    if (t[i]->cfg.key_words > 1 || multi_query_alone(q, grid)) {   // vector tables: their own kernel
       int rc = do_query(t[i], d_keys[i], n[i], d_out_found[i], s);
       if (rc) return rc;
     } else {

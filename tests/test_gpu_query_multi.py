@@ -168,7 +168,9 @@ def test_query_multi_rejects_bad_arguments():
     with pytest.raises(b.HtError):
         b.query_multi([ts], [k])
     tv = b.Table("bucketed", capacity=64, key_words=2)
-    with pytest.raises(b.HtError):
-        b.query_multi([tv], [k])
+    with pytest.raises(b.HtError):                       # vector rows 8-byte aligned, not 16
+        b.ht_query_multi([tv.handle], [k[1:9]], key_words=[2])
+    got = b.query_multi([tv], [k])                       # ten words: five 2-word rows, none stored
+    assert got[0].numel() == 5 and not got[0].any()
     ts.close()
     tv.close()

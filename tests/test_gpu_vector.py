@@ -155,8 +155,8 @@ def test_vec_rejected_uses():
     k = dev(inputs.vector_of_index(np.arange(8), 2, seed=1))
     with pytest.raises(b.HtError):                       # 8-byte aligned, not 16
         b.ht_find_or_put(t.handle, k.reshape(-1)[1:15], key_words=2)
-    with pytest.raises(b.HtError):
-        b.find_or_put_multi([t], [k])
+    with pytest.raises(b.HtError):                       # a misaligned batch in a many-table call
+        b.ht_find_or_put_multi([t.handle], [k.reshape(-1)[1:15]], key_words=[2])
     with pytest.raises(b.HtError):
         t.bfs_explore(inputs.BfsModel(1), 2)
     with pytest.raises(ValueError):
@@ -188,4 +188,75 @@ def test_vec_random_small_tables(kind, w):
         q = np.concatenate([pool, extra])
         assert (query(t, q) == o.query(q)).all(), f"{kind} trial {trial}"
         check_dump(t, o, w, f"{kind} trial {trial}")
+        t.close()
+
+
+def test_vec_many_table_calls():
+    """State-vector tables (2 and 4 words, both designs) in many-table calls
+    beside single-word tables: the one-shot call, a plan launched from a
+    captured HIP graph (replayed onto cleared tables) and the many-table query
+    all equal the oracle."""
+    from oracle import Oracle
+    specs = [("bucketed", dict(bucket_slots=8), 2), ("cuckoo", {}, 4), ("bucketed", dict(bucket_slots=16), 1),
+             ("cuckoo", {}, 2), ("bucketed", dict(bucket_slots=8), 4), ("cuckoo", {}, 1)]
+    batches = []
+    for i, (_, _, w) in enumerate(specs):
+        n = 3000 + 777 * i
+        if w == 1:
+            batches.append(inputs.random_sequence(n, n * 2 // 3, seed=60 + i))
+        else:
+            batches.append(inputs.vector_sequence(n, n * 2 // 3, w, seed=60 + i, structured=bool(i % 2)))
+
+    def make():
+        return [b.Table(k, capacity=8192, key_words=w, **kw) for k, kw, w in specs]
+
+    def oracles():
+        return [VecOracle(w) if w > 1 else Oracle() for _, _, w in specs]
+
+    def check(tables, outs, what):
+        os_ = oracles()
+        for i, (t, (_, _, w)) in enumerate(zip(tables, specs)):
+            exp = os_[i].find_or_put(batches[i])
+            got = outs[i].cpu().numpy()
+            if w == 1:
+                assert np.array_equal(np.sort(batches[i][got == 1]), np.sort(batches[i][exp == 1])), (what, i)
+            else:
+                check_flags(batches[i], got, exp, w, f"{what} table {i}")
+            assert t.size() == os_[i].size, (what, i)
+        return os_
+
+    kd = [dev(x) for x in batches]
+    tables = make()
+    os_ = check(tables, b.find_or_put_multi(tables, kd), "one-shot call")
+    queries = []
+    for i, (_, _, w) in enumerate(specs):
+        fresh = (inputs.uniform_keys(500, seed=80 + i) if w == 1
+                 else inputs.vector_of_index(np.arange(10**6, 10**6 + 500), w, seed=60 + i))
+        queries.append(np.concatenate([batches[i][:700], fresh]))
+    found = b.query_multi(tables, [dev(q) for q in queries])
+    for i in range(len(specs)):
+        assert np.array_equal(found[i].cpu().numpy(), os_[i].query(queries[i])), i
+    for t in tables:
+        t.close()
+
+    tables = make()
+    outs = [torch.empty(len(x), dtype=torch.uint8, device="cuda") for x in batches]
+    plan = b.MultiPlan(tables, kd, outs)
+    g = torch.cuda.CUDAGraph()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(s):
+        with torch.cuda.graph(g, stream=s):
+            plan.launch()
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for t in tables:
+            t.clear()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        check(tables, outs, f"graph replay {rep}")
+    del g
+    plan.close()
+    for t in tables:
         t.close()

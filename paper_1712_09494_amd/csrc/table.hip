@@ -29,12 +29,10 @@ hipError_t cuckoo_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, co
 hipError_t cuckoo_evict(const DevTable&, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, bool, hipStream_t);
 hipError_t cuckoo_single_pass(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
 hipError_t cuckoo_scrub(uint64_t, const CuckooScratch&, uint32_t, hipStream_t);
-hipError_t vec_probe(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
-                     hipStream_t);
 hipError_t vec_evict(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
                       uint32_t, hipStream_t);
-hipError_t vec_claim(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t, uint32_t,
-                     hipStream_t);
+hipError_t vec_find_or_claim(const DevTable&, const uint64_t*, uint64_t, uint8_t*, const CuckooScratch&, uint32_t,
+                             uint32_t, hipStream_t);
 hipError_t vec_commit(const DevTable&, const uint64_t*, uint64_t, const CuckooScratch&, uint32_t, uint32_t,
                       hipStream_t);
 hipError_t vec_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, hipStream_t);
@@ -410,13 +408,10 @@ static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_
   CuckooScratch sc = scratch_view(t, n);
   lane_grid(t, n, 1, blocks, sc.per_wave);
   const uint32_t W = t->cfg.key_words;
+  // one walk looks up and claims, then the commit
   {
-    KernelTimer kt("vec_probe", s);
-    HT_HIP(vec_probe(d, keys, n, out, sc, (uint32_t)blocks, W, s));
-  }
-  {
-    KernelTimer kt("vec_claim", s);
-    HT_HIP(vec_claim(d, keys, n, out, sc, (uint32_t)blocks, W, s));
+    KernelTimer kt("vec_find_or_claim", s);
+    HT_HIP(vec_find_or_claim(d, keys, n, out, sc, (uint32_t)blocks, W, s));
   }
   {
     KernelTimer kt("vec_commit", s);

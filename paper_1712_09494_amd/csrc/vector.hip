@@ -10,14 +10,6 @@ namespace ht {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t vec_probe(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
-                     uint32_t grid, uint32_t W, hipStream_t st) {
-#define HT_L(WW) hipLaunchKernelGGL((vec_probe_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
-  HT_W_DISPATCH(HT_L)
-#undef HT_L
-  return hipGetLastError();
-}
-
 hipError_t vec_evict(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
                       uint32_t grid, uint32_t W, hipStream_t st) {
 #define HT_L(WW) hipLaunchKernelGGL((vec_evict_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
@@ -26,9 +18,10 @@ hipError_t vec_evict(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_
   return hipGetLastError();
 }
 
-hipError_t vec_claim(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, const CuckooScratch& s,
-                     uint32_t grid, uint32_t W, hipStream_t st) {
-#define HT_L(WW) hipLaunchKernelGGL((vec_claim_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
+hipError_t vec_find_or_claim(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out,
+                             const CuckooScratch& s, uint32_t grid, uint32_t W, hipStream_t st) {
+#define HT_L(WW) \
+  hipLaunchKernelGGL((vec_find_or_claim_kernel<WW>), dim3(grid), dim3(kBlock), t.lds, st, t, keys, n, out, s)
   HT_W_DISPATCH(HT_L)
 #undef HT_L
   return hipGetLastError();

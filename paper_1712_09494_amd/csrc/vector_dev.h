@@ -13,25 +13,26 @@
 //
 // Find-or-put, with no kernel reading a vector another lane is still writing
 // and no lane waiting for another:
-//   1. lookup (read-only): compare hash bits, then the arena words; vectors
-//      found report 0, the others are listed with their hash;
-//   2. claim: each listed vector compare-and-swaps a placeholder -- its hash
-//      bits and its batch index -- into the first empty slot of its bucket
-//      sequence (then stash, then overflow set) or, in a Cuckoo table, of its
-//      candidate slots h_1..h_c.  Copies of a vector walk the same slots in
-//      the same order, so a second copy meets the first one's placeholder and
-//      compares the two batch rows (complete before the kernel starts): equal
-//      means it reports 0.  No exchange runs in this kernel, so placeholders
-//      stay where they were put.  One atomic per listed vector;
-//   3. commit: each claimed slot takes an arena entry (one counter atomic per
+//   1. find or claim, one walk per vector: along its bucket sequence (then
+//      stash, then overflow set) or, in a Cuckoo table, the stash and
+//      overflow set and then its candidate slots h_1..h_c.  A stored handle
+//      with the vector's hash bits is compared with the arena words (equal:
+//      present, report 0); an empty slot gets a placeholder -- the hash bits
+//      and the batch index -- by compare-and-swap.  Copies of a vector walk
+//      the same slots in the same order, so a second copy meets the first
+//      one's placeholder and compares the two batch rows (complete before the
+//      kernel starts): equal means it reports 0.  No handle is committed and
+//      no exchange runs in this kernel, so placeholders stay where they were
+//      put.  One atomic per new vector; claims are listed per wave region;
+//   2. commit: each claimed slot takes an arena entry (one counter atomic per
 //      wave), gets the vector's words written there and its placeholder
 //      replaced by the final handle;
 // and for Cuckoo tables, the vectors that found every candidate taken:
-//   4. evict: deduplicated in the scratch set by batch index (equal vectors
+//   3. evict: deduplicated in the scratch set by batch index (equal vectors
 //      compared word by word in the batch); each winner reports 1, takes an
 //      arena entry, writes its words and runs the exchange chain of Sec. 4.1
 //      from h_1 with its handle (then stash, overflow set);
-//   5. scrub the scratch set (the single-word Cuckoo scrub kernel).
+//   4. scrub the scratch set (the single-word Cuckoo scrub kernel).
 // The stash and the overflow list of a vector table are open-addressed sets
 // of handles, probed from positions given by the hash bits.
 // Lookups stop early by the same rules as the single-word tables: a bucket
@@ -45,7 +46,7 @@ namespace ht {
 
 constexpr uint64_t kArenaMask = (1ull << kArenaBits) - 1;
 // Arena indices stay below 2^33; bit 33 of a handle marks a placeholder whose
-// low 33 bits are a batch index (bucketed claim kernel, replaced in commit).
+// low 33 bits are a batch index (find-or-claim kernel, replaced in commit).
 constexpr uint64_t kPlaceBit = 1ull << 33;
 constexpr uint64_t kBatchMask = kPlaceBit - 1;
 
@@ -246,49 +247,11 @@ __device__ inline uint64_t arena_take(const DevTable& t, bool want, uint64_t wav
   return idx;
 }
 
-// Kernel 1: lookup; misses listed per wave region as (hash, batch index).
-template <int W>
-__global__ __launch_bounds__(kBlock) void vec_probe_kernel(DevTable t, const uint64_t* __restrict__ keys,
-                                                            uint64_t n, uint8_t* __restrict__ out,
-                                                            CuckooScratch s) {
-  const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  const int lane = lane_id();
-  const uint64_t begin = wave * s.per_wave;
-  uint64_t end = begin + s.per_wave;
-  if (end > n) end = n;
-  const uint32_t sc = t.ctr->stash_count;
-  const uint32_t oc = t.ctr->overflow_count;
-  uint32_t nlist = 0;
-  for (uint64_t base = begin; base < end; base += kWave) {
-    const uint64_t i = base + lane;
-    bool miss = false;
-    uint64_t H = 0;
-    if (i < end) {
-      uint64_t v[W];
-      load_vec<W>(keys + i * W, v);
-      H = vec_hash<W>(v, t.vseed);
-      if (vec_find<W>(t, H >> kArenaBits, v, sc, oc)) {
-        if (out) out[i] = 0;
-      } else {
-        miss = true;
-      }
-    }
-    const uint64_t mm = ballot(miss);
-    if (miss) {
-      const uint64_t slot = begin + nlist + lanes_below(mm);
-      s.wkey[slot] = H;
-      s.wmeta[slot] = i;
-    }
-    nlist += (uint32_t)__popcll(mm);
-  }
-  if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
-}
-
 // List entry of a vector whose Cuckoo candidates were all taken at claim
 // time: it goes to the evict kernel.
 constexpr uint64_t kLeftover = ~1ull;
 
-// Kernel 4 (Cuckoo): the leftover vectors are deduplicated in the scratch
+// Kernel 3 (Cuckoo): the leftover vectors are deduplicated in the scratch
 // set by batch index (equal vectors compared word by word in the batch);
 // each winner reports 1, takes an arena entry, writes its words and runs the
 // exchange chain of Sec. 4.1 from h_1 with its handle.  Every list entry's
@@ -374,99 +337,130 @@ __device__ __forceinline__ int vec_claim_seen(uint64_t* p, uint64_t hd, uint64_t
   return 0;
 }
 
+// One slot of a bucketed walk that both looks up and claims: a member stored
+// by an earlier call (a committed handle) that holds the vector gives 3;
+// otherwise as vec_claim_seen.  No handle is committed while this runs (the
+// commit kernel comes after), so a failed compare-and-swap only ever returns
+// a placeholder.
 template <int W>
-__device__ __forceinline__ int vec_claim_slot(uint64_t* p, uint64_t ph, uint64_t hb, const uint64_t (&v)[W],
-                                              const uint64_t* __restrict__ keys, uint64_t n) {
-  return vec_claim_seen<W>(p, *p, ph, hb, v, keys, n);
+__device__ __forceinline__ int vec_find_or_claim_seen(const DevTable& t, uint64_t* p, uint64_t hd, uint64_t ph,
+                                                      uint64_t hb, const uint64_t (&v)[W],
+                                                      const uint64_t* __restrict__ keys, uint64_t n) {
+  if (hd != kEmpty && !(hd & kPlaceBit)) return vec_holds<W>(t, hd, hb, v) ? 3 : 0;
+  return vec_claim_seen<W>(p, hd, ph, hb, v, keys, n);
 }
 
-// Kernel 2: claim a slot per distinct listed vector.  Bucketed: along the
-// bucket sequence, then stash, then overflow set.  Cuckoo: among the empty
-// candidate slots h_1..h_c only (no exchange runs in this kernel, so
-// placeholders stay put); a vector that finds every candidate taken is left
-// for the evict kernel.  Locations are numbered slots, then stash, then
-// overflow set; the list entry becomes (claimed location, ~0 for a copy of
-// a claimed vector or kLeftover, hash bits << 33 | batch index).
+// Kernel 1: lookup and claim in one walk.  Bucketed: slots
+// fill as a prefix of each vector's bucket sequence, then the stash, then
+// the overflow set, and none is ever emptied, so the walk meets a stored copy
+// of the vector before the first empty slot it could claim.  Cuckoo: the
+// stash and overflow set are looked up first (a chain that ends there can
+// leave the vector's other candidates empty); then the candidates h_1..h_c
+// in order, a stored copy never lying past an empty candidate when the c
+// indices are distinct (else all c are looked up before any claim); a vector
+// with every candidate taken is left for the evict kernel.  Either way one
+// walk per vector answers "present" or claims a free location, and copies
+// within the batch meet at one placeholder.  Claimed locations (and Cuckoo
+// leftovers, as kLeftover) are listed per wave region as (location, hash
+// bits << 33 | batch index) for the commit and evict kernels.
 template <int W>
-__global__ __launch_bounds__(kBlock) void vec_claim_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,
-                                                            uint8_t* __restrict__ out, CuckooScratch s) {
+__global__ __launch_bounds__(kBlock) void vec_find_or_claim_kernel(DevTable t, const uint64_t* __restrict__ keys,
+                                                                    uint64_t n, uint8_t* __restrict__ out,
+                                                                    CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  const int lane = lane_id();
   const uint64_t begin = wave * s.per_wave;
-  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
+  uint64_t end = begin + s.per_wave;
+  if (end > n) end = n;
   const uint32_t B = t.bucket_slots;
   const uint32_t steps = t.nhash + t.walk;
   const uint64_t nslots = t.nrange * B;
+  const uint32_t sc = t.ctr->stash_count;
+  const uint32_t oc = t.ctr->overflow_count;
+  uint32_t nlist = 0;
   unsigned long long nnew = 0;
-  for (uint32_t e = (uint32_t)lane_id(); e < cnt; e += kWave) {
-    const uint64_t H = s.wkey[begin + e];
-    const uint64_t i = s.wmeta[begin + e];
-    uint64_t v[W];
-    load_vec<W>(keys + i * W, v);
-    const uint64_t hb = H >> kArenaBits;
-    const uint64_t ph = (hb << kArenaBits) | kPlaceBit | i;
-    int st = 0;
-    uint64_t loc = ~0ull;
-    if (t.kind == HT_KIND_CUCKOO) {
+  for (uint64_t base = begin; base < end; base += kWave) {
+    const uint64_t i = base + lane;
+    bool claimed = false, leftover = false;
+    uint64_t loc = ~0ull, hb = 0;
+    if (i < end && t.kind == HT_KIND_CUCKOO) {
+      uint64_t v[W];
+      load_vec<W>(keys + i * W, v);
+      hb = vec_hash<W>(v, t.vseed) >> kArenaBits;
+      const uint64_t ph = (hb << kArenaBits) | kPlaceBit | i;
+      int st = (sc | oc) && vec_stash_query<W>(t, hb, v, sc, oc) ? 3 : 0;
+      if (!st && !hashes_distinct<false>(t, hb)) {
+        for (uint32_t j = 0; j < t.nhash && !st; ++j) {
+          const uint64_t hd = t.slots[hidx<false>(t, hb, j)];
+          if (hd != kEmpty && !(hd & kPlaceBit) && vec_holds<W>(t, hd, hb, v)) st = 3;
+        }
+      }
       for (uint32_t j = 0; j < t.nhash && !st; ++j) {
         const uint64_t sl = hidx<false>(t, hb, j);
-        st = vec_claim_slot<W>(t.slots + sl, ph, hb, v, keys, n);
+        st = vec_find_or_claim_seen<W>(t, t.slots + sl, t.slots[sl], ph, hb, v, keys, n);
         if (st == 1) loc = sl;
       }
-      if (!st) {                                 // every candidate taken: the evict kernel
-        s.wkey[begin + e] = kLeftover;
-        s.wmeta[begin + e] = (hb << 33) | i;
-        continue;
-      }
-      const uint32_t res = st == 2 ? 0u : 1u;
-      nnew += res;
-      if (out) out[i] = (uint8_t)res;
-      s.wkey[begin + e] = loc;
-      s.wmeta[begin + e] = (hb << 33) | i;
-      continue;
-    }
-    uint64_t b = 0;
-    for (uint32_t q = 0; q < steps && !st; ++q) {
-      b = vec_bucket(t, hb, q, b);
-      for (uint32_t c0 = 0; c0 < B && !st; c0 += 8) {
-        uint64_t x[8];
-        load8(t.slots + b * B + c0, x);
-        for (uint32_t k = 0; k < 8 && !st; ++k) {
-          st = vec_claim_seen<W>(t.slots + b * B + c0 + k, x[k], ph, hb, v, keys, n);
-          if (st == 1) loc = b * B + c0 + k;
+      claimed = st == 1;
+      leftover = st == 0;                        // every candidate taken: the evict kernel decides
+      nnew += claimed ? 1u : 0u;
+      if (out && !leftover) out[i] = claimed ? 1 : 0;
+    } else if (i < end) {
+      uint64_t v[W];
+      load_vec<W>(keys + i * W, v);
+      hb = vec_hash<W>(v, t.vseed) >> kArenaBits;
+      const uint64_t ph = (hb << kArenaBits) | kPlaceBit | i;
+      int st = 0;
+      uint64_t b = 0;
+      for (uint32_t q = 0; q < steps && !st; ++q) {
+        b = vec_bucket(t, hb, q, b);
+        for (uint32_t c0 = 0; c0 < B && !st; c0 += 8) {
+          uint64_t x[8];
+          load8(t.slots + b * B + c0, x);
+          for (uint32_t k = 0; k < 8 && !st; ++k) {
+            st = vec_find_or_claim_seen<W>(t, t.slots + b * B + c0 + k, x[k], ph, hb, v, keys, n);
+            if (st == 1) loc = b * B + c0 + k;
+          }
         }
       }
-    }
-    if (!st) {
-      const uint32_t S = t.stash_slots;
-      uint32_t p = stash_start(t, hb);
-      for (uint32_t k = 0; k < S && !st; ++k) {
-        st = vec_claim_slot<W>(t.stash + p, ph, hb, v, keys, n);
-        if (st == 1) {
-          loc = nslots + p;
-          add_agent(&t.ctr->stash_count, 1u);
+      if (!st) {
+        const uint32_t S = t.stash_slots;
+        uint32_t p = stash_start(t, hb);
+        for (uint32_t k = 0; k < S && !st; ++k) {
+          st = vec_find_or_claim_seen<W>(t, t.stash + p, t.stash[p], ph, hb, v, keys, n);
+          if (st == 1) {
+            loc = nslots + p;
+            add_agent(&t.ctr->stash_count, 1u);
+          }
+          p = (p + 1) & (S - 1);
         }
-        p = (p + 1) & (S - 1);
       }
-    }
-    if (!st) {
-      const uint32_t m = t.overflow_slots;
-      uint32_t p = overflow_start(t, hb);
-      for (uint32_t k = 0; k < m && !st; ++k) {
-        st = vec_claim_slot<W>(t.overflow + p, ph, hb, v, keys, n);
-        if (st == 1) {
-          loc = nslots + t.stash_slots + p;
-          add_agent(&t.ctr->overflow_count, 1u);
+      if (!st) {
+        const uint32_t m = t.overflow_slots;
+        uint32_t p = overflow_start(t, hb);
+        for (uint32_t k = 0; k < m && !st; ++k) {
+          st = vec_find_or_claim_seen<W>(t, t.overflow + p, t.overflow[p], ph, hb, v, keys, n);
+          if (st == 1) {
+            loc = nslots + t.stash_slots + p;
+            add_agent(&t.ctr->overflow_count, 1u);
+          }
+          p = p + 1 == m ? 0 : p + 1;
         }
-        p = p + 1 == m ? 0 : p + 1;
       }
+      if (!st) add_agent(&t.ctr->lost, 1u);
+      claimed = st == 1;
+      nnew += claimed ? 1u : 0u;
+      if (out) out[i] = claimed ? 1 : 0;
     }
-    if (!st) add_agent(&t.ctr->lost, 1u);
-    const uint32_t res = st == 2 ? 0u : 1u;
-    nnew += res;
-    if (out) out[i] = (uint8_t)res;
-    s.wkey[begin + e] = loc;                     // for the commit kernel: where, and
-    s.wmeta[begin + e] = (hb << 33) | i;         // which vector with which hash bits
+    const bool listed = claimed || leftover;
+    const uint64_t mm = ballot(listed);
+    if (listed) {
+      const uint64_t slot = begin + nlist + lanes_below(mm);
+      s.wkey[slot] = claimed ? loc : kLeftover;
+      s.wmeta[slot] = (hb << 33) | i;
+    }
+    nlist += (uint32_t)__popcll(mm);
   }
+  if (lane == 0 && begin < n) s.wcnt[wave] = nlist;
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
 }
 
@@ -478,7 +472,7 @@ __device__ __forceinline__ uint64_t* vec_location(const DevTable& t, uint64_t lo
   return t.overflow + (loc - t.stash_slots);
 }
 
-// Kernel 3: the claimed slots get arena entries, the vectors' words and
+// Kernel 2: the claimed slots get arena entries, the vectors' words and
 // their final handles.
 template <int W>
 __global__ __launch_bounds__(kBlock) void vec_commit_kernel(DevTable t, const uint64_t* __restrict__ keys, uint64_t n,

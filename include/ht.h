@@ -102,7 +102,7 @@ enum {
    * slot) instead of a group of B/2 lanes sharing each bucket (Sec. 4.2).
    * Same table, probe sequence and results; a wave serves 64 keys per turn
    * instead of 128/B.  Faster where hits dominate and the table is cache
-   * resident; the many-table launch keeps lane groups. */
+   * resident.  The many-table launch always probes this way. */
   HT_FLAG_BUCKETED_ONE_LANE = 1u << 5
 };
 

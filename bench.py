@@ -895,8 +895,12 @@ def run_served(b, inputs, torch, dev, nreq=4096, ntables=64, slots_log2=24):
     outs = [torch.empty(k.numel(), dtype=torch.uint8, pin_memory=True) for k in keys]
     total = int(sum(k.numel() for k in keys))
     log(f"[bench] served workload: {nreq} requests, {total} keys, {ntables} tables ({time.time() - t0:.1f}s)")
+    # the link the served keys and flags cross: pinned copies of 1 GiB each way
+    pcie = pcie_rates(torch, dev)
+    h2d_bytes, d2h_bytes = 8 * total, total
+    log(f"[bench] pinned copies: host to device {pcie['h2d_GBs']} GB/s, device to host {pcie['d2h_GBs']} GB/s")
     res = {"tables": ntables, "slots_total": ntables << slots_log2, "requests": nreq, "keys": total,
-           "includes_pcie": True, "designs": {}}
+           "includes_pcie": True, "pcie": pcie, "h2d_bytes": h2d_bytes, "d2h_bytes": d2h_bytes, "designs": {}}
     for design, kw in (("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())):
         tables = [b.Table(design, capacity=1 << slots_log2, nhash=3, **kw) for _ in range(ntables)]
 
@@ -918,6 +922,9 @@ def run_served(b, inputs, torch, dev, nreq=4096, ntables=64, slots_log2=24):
             return {"requests_per_s": round(nreq / st["wall_s"], 1),
                     "mkeys_per_s": round(total / st["wall_s"] / 1e6, 1),
                     "wall_s": round(st["wall_s"], 4),
+                    # keys in over the link per second, and as a fraction of a plain pinned copy
+                    "h2d_GBs": round(h2d_bytes / st["wall_s"] / 1e9, 1),
+                    "h2d_frac_of_copy": round(h2d_bytes / st["wall_s"] / 1e9 / pcie["h2d_GBs"], 3),
                     "latency_ms_p50": round(float(np.percentile(lat, 50)), 3),
                     "latency_ms_p99": round(float(np.percentile(lat, 99)), 3),
                     "groups": st["groups"], "merged_launches": st["merged_launches"],
@@ -925,13 +932,15 @@ def run_served(b, inputs, torch, dev, nreq=4096, ntables=64, slots_log2=24):
                     "peak_staging_MB": round(st["peak_staging"] / 2 ** 20, 1)}
 
         zeros = [0.0] * nreq
-        # a backlog replay lasts tens of ms and is bound by the host loop: best of 5
+        # a backlog replay lasts about 0.1 s: best of 5
         seq0 = run(zeros, reps=5, sequential=True)
         sat = seq0["requests_per_s"]
         d = {"saturation_requests_per_s": sat, "sequential_backlog": seq0, "served_backlog": run(zeros, reps=5),
              "poisson": []}
         log(f"[bench] served {design} backlog: sequential {seq0['requests_per_s']} req/s, "
-            f"served {d['served_backlog']['requests_per_s']} req/s")
+            f"served {d['served_backlog']['requests_per_s']} req/s "
+            f"(keys in at {d['served_backlog']['h2d_GBs']} GB/s = {d['served_backlog']['h2d_frac_of_copy']} "
+            f"of a pinned copy)")
         for rho in (0.5, 0.8, 1.2):
             rate = rho * sat
             tr = inputs.served_trace(nreq, ntables, 8, 20, rate=rate, seed=inputs.SEED_BASE + 5, stream=stream)
@@ -948,6 +957,30 @@ def run_served(b, inputs, torch, dev, nreq=4096, ntables=64, slots_log2=24):
             t.close()
         torch.cuda.synchronize()
     return res
+
+
+def pcie_rates(torch, dev, words=1 << 27, reps=3):
+    """Host-to-device and device-to-host rates of plain pinned copies of
+    `words` 64-bit words (1 GiB), best of `reps`, in GB/s."""
+    h = torch.empty(words, dtype=torch.int64, pin_memory=True)
+    d = torch.empty(words, dtype=torch.int64, device=dev)
+    out = {}
+    for name, dst, src in (("h2d_GBs", d, h), ("d2h_GBs", h, d)):
+        dst.copy_(src, non_blocking=True)
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record()
+            dst.copy_(src, non_blocking=True)
+            e1.record()
+            torch.cuda.synchronize()
+            ms = e0.elapsed_time(e1)
+            best = ms if best is None else min(best, ms)
+        out[name] = round(words * 8 / best / 1e6, 1)
+    del h, d
+    return out
 
 
 def cpu_baseline(seq, batch, budget_s=25.0):

@@ -35,4 +35,4 @@ def test_c_client_runs(tmp_path):
     exe = build_client(str(tmp_path / "client"))
     r = subprocess.run([exe], capture_output=True, text=True, timeout=120)
     assert r.returncode == 0, r.stdout + r.stderr
-    assert r.stdout.count(" ok") == 2, r.stdout
+    assert r.stdout.count(" ok") == 6, r.stdout

@@ -217,8 +217,20 @@ def main():
     log(f"[bench] per design {per_design}")
     log(f"[bench] per kernel {per_kernel}")
 
-    # roofline of the dominant kernel (largest total time; clear excluded)
+    # roofline of the dominant kernel (largest total time; clear excluded),
+    # with its memory-side atomic rate beside the chip's random-CAS rate on an
+    # array the size of the table's slots
     rl = roofline(per_kernel, args, d)
+    if rl is not None:
+        atomics = measured_counter(rl["kernel"], "ea_atomics")
+        if atomics is not None and args.batch == 1 << 20 and args.n == 1 << 26:
+            cas = cas_probe_rate(b, torch, dev, stream, cap)
+            rate = atomics / (rl["avg_launch_ms"] * 1e-3) / 1e9
+            rl["atomics"] = {"per_launch": int(atomics), "achieved_Gps": round(rate, 2),
+                             "cas_probe_Gps": cas, "frac": round(rate / cas, 3),
+                             "probe": f"random 64-bit CAS over {cap * 8 / 2 ** 20:.0f} MiB"}
+            log(f"[bench] {rl['kernel']}: {rate:.2f} G atomics/s against {cas} G/s of random CAS "
+                f"({rate / cas:.3f})")
 
     sweep = None
     if not args.no_sweep:
@@ -334,6 +346,29 @@ def kernel_source_hash() -> str:
         with open(os.path.join(csrc, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()
+
+
+def measured_counter(kernel: str, field: str, workload: str = "random_scaling_2p26"):
+    """A per-dispatch figure of `kernel` from the committed counter summary, or
+    None when the summary is missing or the kernels changed since."""
+    p = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
+    try:
+        with open(p) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if c.get("kernel_source_sha256") != kernel_source_hash():
+        return None
+    k = c.get("kernels", {}).get(kernel + "_kernel") or c.get("kernels", {}).get(kernel)
+    return None if k is None or field not in k else float(k[field])
+
+
+def cas_probe_rate(b, torch, dev, stream, words: int, nacc: int = 1 << 26) -> float:
+    """Random 64-bit compare-and-swap rate (G/s) over an array of `words`."""
+    arr = torch.zeros(words, dtype=torch.int64, device=dev)
+    sec = _timed(torch, stream, lambda: b.ht_probe_cas(arr, nacc, 9))
+    del arr
+    return round(nacc / sec / 1e9, 3)
 
 
 def measured_traffic(kernel: str, workload: str = "random_scaling_2p26"):

@@ -223,14 +223,25 @@ def main():
     rl = roofline(per_kernel, args, d)
     if rl is not None:
         atomics = measured_counter(rl["kernel"], "ea_atomics")
-        if atomics is not None and args.batch == 1 << 20 and args.n == 1 << 26:
-            cas = cas_probe_rate(b, torch, dev, stream, cap)
-            rate = atomics / (rl["avg_launch_ms"] * 1e-3) / 1e9
+        fetch_kib = measured_counter(rl["kernel"], "fetch_kib")
+        scale = counter_scale("fetch_scale")
+        if None not in (atomics, fetch_kib, scale) and args.batch == 1 << 20 and args.n == 1 << 26:
+            cas, line = cas_probe_rate(b, torch, dev, stream, cap), line_probe_rate(b, torch, dev, stream, cap)
+            sec = rl["avg_launch_ms"] * 1e-3
+            rate = atomics / sec / 1e9
+            # random lines read: fetched bytes less the batch's keys, in 128-byte lines
+            lines = max(fetch_kib * 1024 * scale - 8 * rl["keys_per_launch"], 0) / 128
+            lrate = lines / sec / 1e9
             rl["atomics"] = {"per_launch": int(atomics), "achieved_Gps": round(rate, 2),
                              "cas_probe_Gps": cas, "frac": round(rate / cas, 3),
                              "probe": f"random 64-bit CAS over {cap * 8 / 2 ** 20:.0f} MiB"}
-            log(f"[bench] {rl['kernel']}: {rate:.2f} G atomics/s against {cas} G/s of random CAS "
-                f"({rate / cas:.3f})")
+            rl["random_lines"] = {"per_launch": int(lines), "achieved_Gps": round(lrate, 2),
+                                  "line_probe_Gps": line, "frac": round(lrate / line, 3),
+                                  "probe": f"random 128-byte line reads over {cap * 8 / 2 ** 20:.0f} MiB"}
+            # the two memory-side resources the kernel shares: near 1 means bound by them
+            rl["lines_plus_atomics_frac"] = round(lrate / line + rate / cas, 3)
+            log(f"[bench] {rl['kernel']}: {rate:.2f} G atomics/s of {cas} G/s random CAS ({rate / cas:.3f}), "
+                f"{lrate:.2f} G lines/s of {line} G/s random reads ({lrate / line:.3f})")
 
     sweep = None
     if not args.no_sweep:
@@ -361,6 +372,25 @@ def measured_counter(kernel: str, field: str, workload: str = "random_scaling_2p
         return None
     k = c.get("kernels", {}).get(kernel + "_kernel") or c.get("kernels", {}).get(kernel)
     return None if k is None or field not in k else float(k[field])
+
+
+def counter_scale(field: str, workload: str = "random_scaling_2p26"):
+    """The calibration factor `field` of the committed counter summary."""
+    try:
+        with open(os.path.join(ROOT, "profiles", f"counters_{workload}.json")) as f:
+            c = json.load(f)
+    except (OSError, ValueError):
+        return None
+    return c.get(field)
+
+
+def line_probe_rate(b, torch, dev, stream, words: int, nacc: int = 1 << 26) -> float:
+    """Random 128-byte line reads (G/s) over an array of `words`."""
+    arr = torch.zeros(words, dtype=torch.int64, device=dev)
+    sink = torch.zeros(4, dtype=torch.int64, device=dev)
+    sec = _timed(torch, stream, lambda: b.ht_probe_gather(arr, nacc, 128, 7, sink))
+    del arr
+    return round(nacc / sec / 1e9, 3)
 
 
 def cas_probe_rate(b, torch, dev, stream, words: int, nacc: int = 1 << 26) -> float:

@@ -259,18 +259,6 @@ __device__ __forceinline__ unsigned long long bucketed_fop_turn(const DevTable& 
   return nnew;
 }
 
-// One wave: find-or-put of keys [begin, end) in turns of G*R keys.
-template <int B, int R, bool SCRIPTED, bool COHERENT>
-__device__ __forceinline__ unsigned long long bucketed_fop_range(const DevTable& t, const uint64_t* __restrict__ keys,
-                                                                 uint64_t begin, uint64_t end,
-                                                                 uint8_t* __restrict__ out) {
-  const uint64_t per = (uint64_t)(kWave / (bucket_width<B>(t) / 2)) * R;
-  unsigned long long nnew = 0;
-  for (uint64_t base = begin; base < end; base += per)
-    nnew += bucketed_fop_turn<B, R, SCRIPTED, COHERENT>(t, keys, base, end, out);
-  return nnew;
-}
-
 // Grid-stride find-or-put: wave w takes turns w, w + nwaves, ...
 template <int B, int R, bool SCRIPTED, bool COHERENT>
 __global__ __launch_bounds__(kBlock) void bucketed_fop_kernel(DevTable t, const uint64_t* __restrict__ keys,

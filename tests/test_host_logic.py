@@ -57,3 +57,16 @@ def test_bench_byte_model():
     assert bench.kernel_bytes("cuckoo_evict", n, d, 3, 8) is None
     h = bench.kernel_source_hash()
     assert len(h) == 64 and h == bench.kernel_source_hash()
+
+
+def test_bench_refuses_more_than_one_gpu():
+    """bench.py measures one GPU: --gpus above 1 exits with status 2 and a
+    message, before touching torch or the GPU."""
+    import os
+    import subprocess
+    import sys
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, os.path.join(root, "bench.py"), "--gpus", "2"], capture_output=True,
+                       text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr and r.stdout == ""

@@ -382,7 +382,10 @@ typedef struct {
   uint32_t slots;           /* launch groups in flight at once (streams), 1..16; 0 = 16 */
   uint32_t merge;           /* requests of distinct tables per launch group; 0 = 16 */
   uint64_t staging_bytes;   /* device staging budget for admission (9 bytes per key,
-                               256-byte pieces); 0 = min(free device memory / 4, 4 GiB) */
+                               256-byte pieces); 0 = min(free device memory / 4, 4 GiB).
+                               Requests of at most 64 KiB of keys do not use it: each
+                               stream slot packs them into an area of its own (1 MiB of
+                               keys and 128 KiB of flags, device and pinned host) */
   uint32_t sequential;      /* 1 = baseline: one request at a time, waiting for each */
   uint32_t reserved;
   uint64_t group_keys;      /* a group stops taking requests at this many keys

@@ -91,8 +91,11 @@ def test_served_equals_alone_and_oracle(cfg, rate):
 
 
 def test_served_admission_throttles_without_changing_results():
-    ntables, cap = 5, 1 << 15
-    reqs = inputs.served_trace(120, ntables, log_min=8, log_max=12, seed=12)
+    """Requests above the small-request size (so they take staging from the
+    budget) under a budget of two of the largest: admission waits, results
+    do not change."""
+    ntables, cap = 5, 1 << 20
+    reqs = inputs.served_trace(60, ntables, log_min=13.2, log_max=16.5, seed=12)
     biggest = max(k.size for _, _, k, _ in reqs)
     budget = 2 * (((biggest * 8 + 255) // 256) * 256 + ((biggest + 255) // 256) * 256)
     tables = make_tables(ntables, cap)
@@ -163,6 +166,25 @@ def test_served_vector_tables_beside_single_word_ones():
             assert np.array_equal(np.sort(d.view(np.uint64)), oras[t].dump())
         else:
             assert np.array_equal(np.sort(_rows(d, w)), np.sort(_rows(oras[t].dump(), w)))
+    srv.close()
+    for t in tables:
+        t.close()
+
+
+def test_served_small_and_large_requests_in_one_group():
+    """Small requests (packed into the slot's area, one copy each way) and
+    large ones (their own staging and copies) mixed within groups, several
+    groups deep: every result equals the oracle's."""
+    ntables, cap = 6, 1 << 20
+    reqs = inputs.served_trace(200, ntables, log_min=4, log_max=17, seed=13)
+    assert any(k.size * 8 > (64 << 10) for _, _, k, _ in reqs) and any(k.size < 1024 for _, _, k, _ in reqs)
+    tables = make_tables(ntables, cap)
+    srv = b.Server(tables, slots=3, merge=16)
+    outs, admit, done, groups, st = srv.run([(op, t, pinned(k), a) for op, t, k, a in reqs])
+    ora, os_ = oracle_run(reqs, ntables)
+    compare(reqs, [o.numpy() for o in outs], ora, "small and large")
+    for t in range(ntables):
+        assert np.array_equal(np.sort(b.u64(tables[t].dump())), os_[t].dump())
     srv.close()
     for t in tables:
         t.close()

@@ -188,3 +188,38 @@ def test_served_small_and_large_requests_in_one_group():
     srv.close()
     for t in tables:
         t.close()
+
+
+def test_served_requests_at_the_packing_size():
+    """Requests of exactly 64 KiB of keys (packed into the slot's area) and
+    one key more (their own staging), single-word and 4-word vector tables,
+    in the same groups: every result equals the oracle's."""
+    from oracle import VecOracle
+    tables = [b.Table("bucketed", capacity=1 << 17, bucket_slots=8), b.Table("cuckoo", capacity=1 << 17),
+              b.Table("bucketed", capacity=1 << 16, key_words=4), b.Table("cuckoo", capacity=1 << 16, key_words=4)]
+    words = [1, 1, 4, 4]
+    oras = [Oracle(), Oracle(), VecOracle(4), VecOracle(4)]
+    reqs = []
+    for rnd in range(3):
+        for t, w in enumerate(words):
+            rows = (64 << 10) // (8 * w) + (rnd % 2)          # at the size, then one key above
+            if w == 1:
+                keys = inputs.random_sequence(rows, rows - rows // 5, seed=900 + 10 * rnd + t)
+            else:
+                keys = inputs.vector_sequence(rows, rows - rows // 5, w, seed=900 + 10 * rnd + t)
+            reqs.append(("fop" if rnd < 2 else "query", t, keys, 0.0))
+    srv = b.Server(tables, slots=2, merge=4)
+    outs, _, _, _, st = srv.run([(op, t, pinned(k), a) for op, t, k, a in reqs])
+    for i, (op, t, keys, _) in enumerate(reqs):
+        got = outs[i].numpy()
+        if op == "query":
+            check_query_r1(got, oras[t].query(keys), f"req {i}")
+        elif words[t] == 1:
+            check_flags_r2(keys, got, oras[t].find_or_put(keys), f"req {i}")
+        else:
+            exp = oras[t].find_or_put(keys)
+            v = _rows(keys, 4)
+            assert np.array_equal(np.sort(v[got == 1]), np.sort(v[exp == 1])), f"req {i}"
+    srv.close()
+    for t in tables:
+        t.close()

@@ -215,3 +215,25 @@ def first_occurrence_flags_vec(keys, w: int) -> np.ndarray:
         _, first = np.unique(v, return_index=True)
         out[first] = 1
     return out
+
+
+def set_digest(keys) -> dict:
+    """Order-free fingerprint of a set of 64-bit keys, for comparing sets too
+    large to store: the member count, and the sum (mod 2^64) and the xor of
+    two multiply-xorshift mixes of every member.  Two sets with equal digests
+    are equal with overwhelming probability.  ``keys`` must hold each member
+    once (the count is the array length)."""
+    k = _as_u64(keys).reshape(-1)
+    with np.errstate(over="ignore"):
+        a = k * U64(0x9E3779B97F4A7C15)
+        a ^= a >> U64(29)
+        a *= U64(0xBF58476D1CE4E5B9)
+        a ^= a >> U64(32)
+        b = (k ^ U64(0x5851F42D4C957F2D)) * U64(0xD6E8FEB86659FD93)
+        b ^= b >> U64(31)
+        b *= U64(0x94D049BB133111EB)
+        b ^= b >> U64(29)
+        s = int(np.sum(a, dtype=np.uint64)) if k.size else 0
+        x = int(np.bitwise_xor.reduce(b)) if k.size else 0
+    return {"count": int(k.size), "sum": f"{s:016x}", "xor": f"{x:016x}"}
+

@@ -2,7 +2,10 @@
 
 Levels 0-4 are compared with the oracle's BFS (same batch multisets, same new
 states); the full seven levels (a 715,127,564-key batch, 121,210,369 states)
-are checked against the recorded calibration counts of the workload."""
+are checked against tests/golden/bfs_calibration.json, written by the
+oracle-only script beside it: every level's batch size and visited count,
+and the visited set itself through its digest (count, sum and xor of two
+mixes of every member)."""
 import json
 import os
 
@@ -11,7 +14,7 @@ import pytest
 
 torch = pytest.importorskip("torch")
 
-from oracle import Oracle  # noqa: E402
+from oracle import Oracle, set_digest  # noqa: E402
 from paper_1712_09494_amd import binding as b  # noqa: E402
 from paper_1712_09494_amd import inputs  # noqa: E402
 
@@ -49,6 +52,13 @@ def test_bfs_levels_match_oracle(kind, kw):
         assert t.size() == o.size
 
 
+def check_visited_set(t, g):
+    """The table's members equal the oracle's visited set after the last
+    level (digest of the dump: count, sum and xor of two mixes)."""
+    dump = b.u64(t.dump())
+    assert set_digest(dump) == g["visited_digest"][-1]
+
+
 @pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
 def test_bfs_full_size_seed1(kind, kw):
     g = golden()["seed1"]
@@ -56,17 +66,21 @@ def test_bfs_full_size_seed1(kind, kw):
     with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, **kw) as t:
         r = t.bfs_explore(inputs.BfsModel(1), 7)
         assert r["batch_sizes"] == g["batch_sizes"]
+        assert r["new_counts"] == g["new_counts"]
         assert list(1 + np.cumsum(r["new_counts"])) == visited
         assert t.size() == visited[-1]
         assert t.sync_status() == b.HT_OK
+        check_visited_set(t, g)
 
 
-def test_bfs_full_size_seed2():
+@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+def test_bfs_full_size_seed2(kind, kw):
     g = golden()["seed2"]
-    with b.Table("bucketed", capacity=int(np.ceil(g["visited_after_level6"] / 0.7)), nhash=3, bucket_slots=8) as t:
+    with b.Table(kind, capacity=int(np.ceil(g["visited_after"][-1] / 0.7)), nhash=3, **kw) as t:
         r = t.bfs_explore(inputs.BfsModel(2), 7)
-        v = list(1 + np.cumsum(r["new_counts"]))
-        assert v[5] == g["visited_after_level5"] and v[6] == g["visited_after_level6"]
+        assert r["batch_sizes"] == g["batch_sizes"]
+        assert list(1 + np.cumsum(r["new_counts"])) == g["visited_after"]
+        check_visited_set(t, g)
 
 
 FUSED = [("bucketed", dict(bucket_slots=8)), ("bucketed", dict(bucket_slots=16)),
@@ -132,6 +146,7 @@ def test_bfs_fused_full_size_seed1(kind, kw):
         assert list(1 + np.cumsum(r["new_counts"])) == visited
         assert t.size() == visited[-1]
         assert t.sync_status() == b.HT_OK
+        check_visited_set(t, g)
 
 
 def test_bfs_split_level_times():

@@ -15,7 +15,7 @@ import numpy as np
 import pytest
 
 from oracle import (LoopOracle, Oracle, VecLoopOracle, VecOracle, first_occurrence_flags,
-                    first_occurrence_flags_vec)
+                    first_occurrence_flags_vec, set_digest)
 from paper_1712_09494_amd import inputs
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -136,12 +136,42 @@ def _bfs_counts(seed, levels):
 
 
 def test_bfs_calibration_counts():
-    """Generator + oracle reproduce the recorded counts of the BFS workload."""
+    """Generator + oracle reproduce the stored counts and set digests of the
+    BFS workload for levels 0-4 (the script beside the golden file writes all
+    seven levels the same way), and the stored file is consistent: visited
+    counts are 1 + the running sum of new states, the digests' counts agree,
+    and the counts of seed 1 are those recorded when the workload was
+    specified (121,210,369 states after level 6; seed 2: 11,163,058 after
+    level 5 and 75,904,606 after level 6)."""
+    with open(os.path.join(GOLDEN, "bfs_calibration.json")) as f:
+        gall = json.load(f)
+    assert gall["command"] == "python tests/golden/make_bfs_calibration.py"
+    for seed in (1, 2):
+        g = gall[f"seed{seed}"]
+        sizes, visited = _bfs_counts(seed, 5)
+        assert sizes == g["batch_sizes"][:5]
+        assert visited == g["visited_after"][:5]
+        assert g["visited_after"] == [int(x) for x in 1 + np.cumsum(g["new_counts"])]
+        assert [x["count"] for x in g["visited_digest"]] == g["visited_after"]
+        assert [x["count"] for x in g["new_digest"]] == g["new_counts"]
+    assert gall["seed1"]["visited_after"][-1] == 121210369
+    assert gall["seed1"]["batch_sizes"][-1] == 715127564
+    assert gall["seed2"]["visited_after"][5:] == [11163058, 75904606]
+
+
+def test_bfs_calibration_digests_levels_0_to_3():
+    """The stored digests of the visited set and of each level's new states
+    equal the digests of the oracle's BFS for the first levels."""
     with open(os.path.join(GOLDEN, "bfs_calibration.json")) as f:
         g = json.load(f)["seed1"]
-    sizes, visited = _bfs_counts(1, 5)
-    assert sizes == g["batch_sizes"][:5]
-    assert visited == g["visited_after"][:5]
+    model = inputs.BfsModel(1)
+    o = Oracle([model.initial_state])
+    frontier = np.array([model.initial_state], dtype=np.uint64)
+    for level in range(4):
+        batch = model.successors(frontier)
+        frontier = batch[o.find_or_put(batch) == 1]
+        assert set_digest(o.dump()) == g["visited_digest"][level]
+        assert set_digest(frontier) == g["new_digest"][level]
 
 
 class _LastWins(Oracle):

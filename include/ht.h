@@ -454,6 +454,20 @@ int ht_probe_gather(const uint64_t* d_array, uint64_t n_words, uint64_t n_access
 int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access,
                  uint64_t seed, hipStream_t stream);
 
+/* The memory pattern of a find-or-put kernel, without the table logic: for
+ * each of n_items keys (device), read the key, make `lines_per_item` random
+ * 8-byte reads (on average; each costs a whole line at the memory) in
+ * d_array (n_words 64-bit words, device), then with probability
+ * `cas_per_item` one random 64-bit compare-and-swap (empty -> key) there,
+ * and write a 1-byte flag to d_out.  Fractions are met per item by a keyed
+ * draw, in steps of 1/256.  Its time against a table kernel's on the same
+ * keys, with the kernel's own read and compare-and-swap counts, tells how
+ * close the kernel is to what the memory system allows for that mix.
+ * HT_EINVAL for NULL pointers, an empty array, lines outside 0..64 or a
+ * probability outside 0..1. */
+int ht_probe_mix(const uint64_t* d_keys, uint8_t* d_out, uint64_t n_items, uint64_t* d_array, uint64_t n_words,
+                 double lines_per_item, double cas_per_item, uint64_t seed, hipStream_t stream);
+
 #ifdef __cplusplus
 }
 #endif

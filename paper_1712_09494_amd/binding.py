@@ -218,6 +218,7 @@ _PROTOS = {
     "ht_probe_copy": (C.c_int, [_vp, _vp, _u64, _vp]),
     "ht_probe_gather": (C.c_int, [_vp, _u64, _u64, _u32, _u64, _vp, _vp]),
     "ht_probe_cas": (C.c_int, [_vp, _u64, _u64, _u64, _vp]),
+    "ht_probe_mix": (C.c_int, [_vp, _vp, _u64, _vp, _u64, C.c_double, C.c_double, _u64, _vp]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -511,6 +512,12 @@ def ht_probe_gather(arr, n_access: int, line_bytes: int, seed: int, sink, stream
 def ht_probe_cas(arr, n_access: int, seed: int, stream=None) -> None:
     _check(load().ht_probe_cas(arr.data_ptr(), arr.numel(), n_access, seed & EMPTY, _stream_handle(stream)),
            "ht_probe_cas")
+
+
+def ht_probe_mix(keys, out, arr, lines_per_item: float, cas_per_item: float, seed: int, stream=None) -> None:
+    _check(load().ht_probe_mix(keys.data_ptr(), out.data_ptr(), keys.numel(), arr.data_ptr(), arr.numel(),
+                               float(lines_per_item), float(cas_per_item), seed & EMPTY, _stream_handle(stream)),
+           "ht_probe_mix")
 
 
 # ---- object wrapper --------------------------------------------------------------

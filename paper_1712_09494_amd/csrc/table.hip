@@ -46,6 +46,8 @@ hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_
 hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
                         hipStream_t);
 hipError_t probe_cas(uint64_t*, uint64_t, uint64_t, uint64_t, uint32_t, hipStream_t);
+hipError_t probe_mix(const uint64_t*, uint8_t*, uint64_t, uint64_t*, uint64_t, uint32_t, uint32_t, uint64_t, uint32_t,
+                     hipStream_t);
 }  // namespace ht
 
 using namespace ht;
@@ -1054,6 +1056,21 @@ int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access, uint64_
   int dev = 0;
   (void)hipGetDevice(&dev);
   HT_HIP(probe_cas(d_array, n_words, n_access, seed, device_cus(dev) * 8, s));
+  return HT_OK;
+}
+
+int ht_probe_mix(const uint64_t* d_keys, uint8_t* d_out, uint64_t n_items, uint64_t* d_array, uint64_t n_words,
+                 double lines_per_item, double cas_per_item, uint64_t seed, hipStream_t s) {
+  if (n_items == 0) return HT_OK;
+  if (!d_keys || !d_out || !d_array || n_words == 0) return fail(HT_EINVAL, "NULL pointer or empty array");
+  if (!(lines_per_item >= 0.0 && lines_per_item <= 64.0)) return fail(HT_EINVAL, "lines_per_item outside 0..64");
+  if (!(cas_per_item >= 0.0 && cas_per_item <= 1.0)) return fail(HT_EINVAL, "cas_per_item outside 0..1");
+  const uint32_t lq = (uint32_t)(lines_per_item * 256.0 + 0.5);
+  const uint32_t cq = (uint32_t)(cas_per_item * 256.0 + 0.5);
+  int dev = 0;
+  (void)hipGetDevice(&dev);
+  KernelTimer kt("probe_mix", s);
+  HT_HIP(probe_mix(d_keys, d_out, n_items, d_array, n_words, lq, cq, seed, device_cus(dev) * 8, s));
   return HT_OK;
 }
 

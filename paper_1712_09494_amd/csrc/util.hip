@@ -110,6 +110,42 @@ __global__ __launch_bounds__(kBlock) void probe_cas_kernel(uint64_t* __restrict_
   }
 }
 
+// Mixed probe: the memory pattern of a find-or-put kernel without the table
+// logic.  One lane per item: read the item's 8-byte key (coalesced), make
+// `lines` random 8-byte reads (whole lines at the memory) at addresses mixed
+// from the key, then with probability `cas` one random 64-bit
+// compare-and-swap (empty -> key) whose address depends on the words read,
+// and write a 1-byte flag (coalesced).  Fractional counts are met per item by
+// a keyed draw: lines_q / 256 reads on average, cas_q / 256 CAS.
+__global__ __launch_bounds__(kBlock) void probe_mix_kernel(const uint64_t* __restrict__ keys,
+                                                           uint8_t* __restrict__ out, uint64_t nitems,
+                                                           uint64_t* __restrict__ a, uint64_t nwords,
+                                                           uint32_t lines_q, uint32_t cas_q, uint64_t seed) {
+  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
+  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nitems; i += stride) {
+    const uint64_t k = keys[i];
+    const uint64_t r = mix64(k ^ seed ^ 0x243f6a8885a308d3ull);
+    const uint32_t nl = (lines_q >> 8) + (((uint32_t)r & 255u) < (lines_q & 255u) ? 1u : 0u);
+    uint64_t acc = 0;
+    for (uint32_t l = 0; l < nl; ++l) acc ^= a[mulhi64(mix64(k ^ seed ^ (0x9e3779b97f4a7c15ull * (l + 1))), nwords)];
+    uint8_t f = (uint8_t)(acc & 1);
+    if (((uint32_t)(r >> 8) & 255u) < cas_q) {
+      const uint64_t h = mix64(k ^ seed ^ (acc & 0x100));   // issued after the reads complete
+      f = cas64(&a[mulhi64(h, nwords)], kEmpty, k) == kEmpty ? 1 : 0;
+    }
+    out[i] = f;
+  }
+}
+
+hipError_t probe_mix(const uint64_t* keys, uint8_t* out, uint64_t nitems, uint64_t* a, uint64_t nwords,
+                     uint32_t lines_q, uint32_t cas_q, uint64_t seed, uint32_t grid, hipStream_t s) {
+  const uint64_t need = (nitems + kBlock - 1) / kBlock;
+  const uint32_t g = (uint32_t)(need < grid ? need : grid);
+  hipLaunchKernelGGL(probe_mix_kernel, dim3(g), dim3(kBlock), 0, s, keys, out, nitems, a, nwords, lines_q, cas_q,
+                     seed);
+  return hipGetLastError();
+}
+
 hipError_t probe_copy(const uint64_t* src, uint64_t* dst, uint64_t n, uint32_t grid, hipStream_t s) {
   const uint64_t n2 = n / 2;
   hipLaunchKernelGGL(probe_copy_kernel, dim3(grid), dim3(kBlock), 0, s,

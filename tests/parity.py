@@ -45,3 +45,34 @@ def check_dump_r3(dump, oracle_keys, size, what=""):
     assert d.size == np.unique(d).size, f"{what}: a key is stored twice"
     assert d.size == o.size and np.array_equal(d, o), f"{what}: dump {d.size} vs oracle {o.size}"
     assert size == o.size, f"{what}: size {size} vs {o.size}"
+
+
+def check_flags_r2_calls(keys, gpu, ora, bounds, what=""):
+    """R2 for every call of a run of consecutive calls, exactly and in time
+    linear in the keys.  ``ora`` are the oracle's flags for the same calls
+    (the sequential set definition: for a run starting from an empty set,
+    ``first_occurrence_flags`` of the whole sequence); ``bounds`` are the
+    calls' start indices followed by the end.  Where the two flag arrays
+    differ, the keys reported new only by the GPU and only by the oracle must
+    be the same multiset within each call; where they agree there is nothing
+    to compare.  So for every call and key the number of occurrences reported
+    new is the oracle's (0 or 1)."""
+    keys = as_u64(keys)
+    gpu = np.asarray(gpu, dtype=np.uint8)
+    ora = np.asarray(ora, dtype=np.uint8)
+    assert gpu.shape == keys.shape == ora.shape, what
+    bad = np.flatnonzero(gpu > 1)
+    assert bad.size == 0, f"{what}: flags outside {{0,1}} at {bad[:8]} (values {gpu[bad[:8]]})"
+    diff = np.flatnonzero(gpu != ora)
+    g = diff[gpu[diff] == 1]
+    o = diff[ora[diff] == 1]
+    assert g.size == o.size, f"{what}: {g.size} keys new only on the GPU, {o.size} only in the oracle"
+    if g.size == 0:
+        return
+    bounds = np.asarray(bounds, dtype=np.int64)
+    call_g = np.searchsorted(bounds, g, side="right")
+    call_o = np.searchsorted(bounds, o, side="right")
+    gi = np.lexsort((call_g, keys[g]))
+    oi = np.lexsort((call_o, keys[o]))
+    assert np.array_equal(keys[g][gi], keys[o][oi]) and np.array_equal(call_g[gi], call_o[oi]), \
+        f"{what}: keys reported new differ from the oracle's within a call"

@@ -77,6 +77,7 @@ def parse():
                     help="only run the memory-system probes (copy, random gather, random CAS)")
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own designs on the W2 fill")
     ap.add_argument("--no-mix", action="store_true", help="skip the mixed memory-pattern probes")
+    ap.add_argument("--no-evict-profile", action="store_true", help="skip the eviction-chain profile")
     ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
                     help="file for the full results (the stdout line carries the headline); '' = none")
     return ap.parse_args()
@@ -290,9 +291,17 @@ def main():
     if rls:
         dom = max(rls, key=lambda k: per_kernel[k]["total_ms"])
         res["roofline"] = dict(rls[dom], kernel=dom)
-    evict = per_kernel.get("cuckoo_evict")
-    if evict and "cuckoo" in tables:
-        res["cuckoo_evict"] = evict_profile(b, torch, tables["cuckoo"], keys, out, args.n, args.batch)
+    if "cuckoo" in tables and not args.no_evict_profile:
+        # the evict kernel's launches and chains, with the plain chain of Sec. 4.1
+        # and with the lookahead before each exchange
+        res["cuckoo_evict"] = evict_profile(b, torch, cap, keys, out, args.n, args.batch)
+        res["cuckoo_evict_lookahead"] = evict_profile(b, torch, cap, keys, out, args.n, args.batch,
+                                                      flags=b.HT_FLAG_CUCKOO_LOOKAHEAD)
+        for k in ("cuckoo_evict", "cuckoo_evict_lookahead"):
+            r = res[k]
+            log(f"[bench] {k}: avg {r['avg_ms']} ms, max {r['max_ms']} ms, fill kernels {r['fill_kernels_ms']} ms, "
+                f"chains mean {r['chains']['mean']} p99 {r['chains']['p99']} max {r['chains']['max']}, "
+                f"stash {r['stash']}")
 
     if not args.no_sweep:
         res["sweep"] = run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out)
@@ -423,6 +432,7 @@ def headline(res: dict) -> dict:
     w1 = res.get("w1")
     w1_sum = {k: [v["fop_mops"], v.get("frac_of_mix")] for k, v in w1["designs"].items()} if w1 else None
     ev = res.get("cuckoo_evict")
+    evl = res.get("cuckoo_evict_lookahead")
     line = {
         "metric": METRIC,
         "value": res.get("value"),
@@ -445,9 +455,9 @@ def headline(res: dict) -> dict:
                                  "paper_gt750m_32bit": "Cuckoo 4.6-6.0x GPUexplore (Table 1, non-random); "
                                                        "about 3x (random)"},
         "other_kernels": others or None,
-        "cuckoo_evict": dict({k: ev.get(k) for k in ("avg_ms", "max_ms")},
-                             chains={k: (ev.get("chains") or {}).get(k) for k in ("mean", "p99", "max")})
-        if ev else None,
+        "cuckoo_evict": {name: dict({k: e.get(k) for k in ("avg_ms", "max_ms")},
+                                    chains=[(e.get("chains") or {}).get(k) for k in ("mean", "p99", "max")])
+                         for name, e in (("chain", ev), ("lookahead", evl)) if e} or None,
         "sweep_fop_mops_b16_b20_b24": sweep_sum,
         "w1_fop_mops_frac_of_mix": w1_sum,
         "bfs": bfs_sum,
@@ -563,33 +573,36 @@ def mix_probe(b, torch, dev, stream, keys, words, lines, cas, kernel_ms, reps=5)
             "array_MiB": round(words * 8 / 2 ** 20, 1)}
 
 
-def evict_profile(b, torch, t, keys, out, n, batch):
-    """Per-launch durations of the Cuckoo evict kernel over one fill of the
-    table (the library's per-kernel events, read after every batch) and the
-    exchanges of the fill."""
+def evict_profile(b, torch, cap, keys, out, n, batch, flags=0):
+    """Per-launch durations of the Cuckoo evict kernel over one W2 fill of a
+    table of `cap` slots (c = 3) created with the chain-length histogram on
+    (the library's per-kernel events, read after every batch; a warm-up fill
+    first), the exchanges of the fill and the histogram of its chains."""
+    t = b.Table("cuckoo", capacity=cap, nhash=3, max_batch=batch, flags=flags | b.HT_FLAG_CHAIN_STATS)
+    for s0 in range(0, n, batch):
+        t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
     t.clear()
     torch.cuda.synchronize()
     b.ht_timing_enable(True)
-    per, prev = [], 0.0
+    per, prev, fill_ms = [], 0.0, 0.0
     for s0 in range(0, n, batch):
         t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
         torch.cuda.synchronize()
-        total = b.ht_timing_report().get("cuckoo_evict", (0, 0.0))[1]
+        rep = b.ht_timing_report()
+        total = rep.get("cuckoo_evict", (0, 0.0))[1]
+        fill_ms = sum(v[1] for k, v in rep.items() if k.startswith("cuckoo_"))
         per.append(total - prev)
         prev = total
     b.ht_timing_enable(False)
     st = t.stats()
+    hist = b.ht_chain_histogram(t.handle)
+    t.close()
     per = np.array(per)
     return {"avg_ms": round(float(per.mean()), 5), "max_ms": round(float(per.max()), 5),
             "p99_ms": round(float(np.percentile(per, 99)), 5), "launches": int(per.size),
-            "evictions": int(st["evictions"]), "chains": chain_histogram(b, t)}
-
-
-def chain_histogram(b, t):
-    """Eviction-chain lengths of the table's fills so far, when the library
-    reports them (None otherwise)."""
-    fn = getattr(b, "ht_chain_histogram", None)
-    return None if fn is None else fn(t.handle)
+            "per_launch_ms": [round(float(x), 5) for x in per],
+            "fill_kernels_ms": round(fill_ms, 3), "evictions": int(st["evictions"]),
+            "stash": int(st["stash_count"]), "chains": hist}
 
 
 # Sources that define or launch the kernels of the counted workload (the

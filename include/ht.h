@@ -39,7 +39,14 @@
  * 0 = the key was already present (or another copy in the batch reported 1),
  * 2 = the key was absent and could not be placed in its buckets nor the stash;
  * it is kept on the table's overflow list (still a member, found by query)
- * until ht_rebuild.  An overflowed key may report 2 more than once.
+ * until ht_rebuild.  An overflowed key may report 2 more than once.  Only when
+ * the overflow list is full as well is such a key not kept: it still reports
+ * 2, is counted in ht_stats_t.lost, and is not a member; ht_sync_status
+ * reports HT_EFULL in both cases (Sec. 4.1 and 4.2: the table is full and is
+ * to be rebuilt with new hash constants).
+ *
+ * Entry points without a defining passage in the paper (memory management,
+ * introspection, test and measurement aids) say "Infrastructure".
  */
 #ifndef HT_H
 #define HT_H
@@ -103,7 +110,17 @@ enum {
    * Same table, probe sequence and results; a wave serves 64 keys per turn
    * instead of 128/B.  Faster where hits dominate and the table is cache
    * resident.  The many-table launch always probes this way. */
-  HT_FLAG_BUCKETED_ONE_LANE = 1u << 5
+  HT_FLAG_BUCKETED_ONE_LANE = 1u << 5,
+  /* Measurement: record each Cuckoo eviction chain's number of exchanges in
+   * a histogram read by ht_chain_histogram (one extra atomic per chain). */
+  HT_FLAG_CHAIN_STATS = 1u << 6,
+  /* Cuckoo: before each exchange of the eviction chain (Sec. 4.1), a key
+   * evicted from h_a reads its candidates h_{a+1}..h_c and compare-and-swaps
+   * itself into the lowest-numbered empty one; the chain goes on by exchange
+   * only when none is empty.  Fewer exchanges, one more read per step.  Not
+   * combinable with HT_FLAG_CUCKOO_PAPER_ORDER (which keeps the insertion of
+   * Sec. 4.1 as written). */
+  HT_FLAG_CUCKOO_LOOKAHEAD = 1u << 7
 };
 
 typedef struct {
@@ -156,7 +173,8 @@ typedef struct {
   uint64_t seed;           /* current hash seed (changes on rebuild) */
 } ht_stats_t;
 
-/* Fills *cfg with the defaults for `kind` (capacity and seed left 0). */
+/* Infrastructure.  Fills *cfg with the defaults for `kind` (capacity and
+ * seed left 0). */
 void ht_config_default(ht_config* cfg, uint32_t kind);
 
 /* Create a table (Sec. 5: the table is allocated on the device and its hash
@@ -166,10 +184,12 @@ void ht_config_default(ht_config* cfg, uint32_t kind);
  * allocation fails. */
 int ht_create(const ht_config* cfg, ht_table** out);
 
-/* ht_create with defaults for everything but kind, capacity and nhash. */
+/* Infrastructure.  ht_create with defaults for everything but kind,
+ * capacity and nhash. */
 int ht_create_simple(uint32_t kind, uint64_t capacity, uint32_t nhash, ht_table** out);
 
-/* Free the table's device memory (synchronises the device first). */
+/* Infrastructure.  Free the table's device memory (synchronises the device
+ * first); HT_EINVAL for a NULL table. */
 int ht_destroy(ht_table* t);
 
 /* Find-or-put (Sec. 5; Sec. 4.1 insertion for cuckoo, Sec. 4.2 for bucketed).
@@ -222,7 +242,8 @@ int ht_query_multi(ht_table* const* t, const uint64_t* const* d_keys,
 
 typedef struct ht_multi_plan ht_multi_plan;
 
-/* Prepare a many-table find-or-put: validates the arguments (as
+/* The find-or-insert of Sec. 5 for many tables, prepared once and launched
+ * many times.  Prepare a many-table find-or-put: validates the arguments (as
  * ht_find_or_put_multi), reserves each Cuckoo and state-vector table's
  * scratch for its batch, and copies the tables' descriptors and work-item
  * lists to the device (allocates, synchronises).  The key and flag buffers
@@ -231,7 +252,8 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
                          const uint64_t* n, uint8_t* const* d_out_is_new,
                          uint32_t ntables, ht_multi_plan** out);
 
-/* Run the plan on `stream`: one persistent kernel for the bucketed tables,
+/* The find-or-put of Sec. 5 (Sec. 4.1 and 4.2 insertion) of every table of
+ * the plan.  Run the plan on `stream`: one persistent kernel for the bucketed tables,
  * then three phase kernels covering every Cuckoo table, then each
  * state-vector table's own kernels.
  * Allocates nothing, uses no memset and does not synchronise, so it may be
@@ -239,62 +261,96 @@ int ht_multi_plan_create(ht_table* const* t, const uint64_t* const* d_keys,
  * its tables, must be ordered on one stream. */
 int ht_multi_plan_launch(ht_multi_plan* p, hipStream_t stream);
 
-/* Synchronises `stream`; HT_EHIP if it reports an error, else HT_OK. */
+/* Infrastructure.  Synchronises `stream`; HT_EHIP if it reports an error,
+ * else HT_OK; HT_EINVAL for a NULL plan. */
 int ht_multi_plan_status(ht_multi_plan* p, hipStream_t stream);
 
-/* Free the plan's device memory (synchronises the device). */
+/* Infrastructure.  Free the plan's device memory (synchronises the device);
+ * HT_EINVAL for a NULL plan. */
 int ht_multi_plan_destroy(ht_multi_plan* p);
 
-/* Synchronises `stream`; HT_EFULL if keys went to the overflow list (or were
- * lost) since the table was created or last rebuilt, else HT_OK. */
+/* The "table full" report (Sec. 4.1: a key left over after the eviction
+ * chain and the stash means the table must be rebuilt with new hash
+ * constants; Sec. 4.2: the bucketed table is considered full when all c
+ * buckets of a key are full).  Synchronises `stream`; HT_EFULL if keys went
+ * to the overflow list (or were lost, see above) since the table was created,
+ * cleared or last rebuilt, else HT_OK. */
 int ht_sync_status(ht_table* t, hipStream_t stream);
 
 /* Rebuild (Sec. 4.1: when the stash overflows the table is rebuilt with new
  * hash constants): draws new constants, optionally grows to new_capacity
- * slots (0 = keep), and re-inserts every member (slots, stash, overflow).
- * Synchronises. */
+ * slots (0 = keep), and re-inserts every member (slots, stash, overflow list,
+ * the all-ones key) into new storage.  The new storage is allocated before
+ * the old is released, and the old table is kept until every member is
+ * placed in slots or stash: up to 8 sets of constants are tried, and when
+ * none places them all (HT_EFULL) or an allocation fails (HT_ENOMEM) the
+ * table is left exactly as it was, every member kept.  Needs device memory
+ * for the old and new storage at once.  HT_EINVAL for new_capacity above
+ * 2^40 slots (2^33 entries for state-vector tables).  Synchronises. */
 int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t stream);
 
-/* *out_n = number of distinct keys stored.  Synchronises. */
+/* The size of the set of inserted elements (Sec. 5: find-or-put stores each
+ * distinct element once): *out_n = number of distinct keys stored (slots,
+ * stash, overflow list).  HT_EINVAL for a NULL out_n.  Synchronises. */
 int ht_size(ht_table* t, uint64_t* out_n, hipStream_t stream);
 
-/* Write every member once (any order) to d_out (device, room for `cap`
- * keys; a vector table writes rows of key_words words); *out_n = member
- * count (even when it exceeds cap, in which case only cap keys are written).
- * Synchronises. */
+/* The set of inserted elements (Sec. 5): write every member once (any
+ * order) to d_out (device, room for `cap` keys; a vector table writes rows of
+ * key_words words); *out_n = member count (even when it exceeds cap, in which
+ * case only cap keys are written).  HT_EINVAL for a NULL out_n, or a NULL
+ * d_out with cap > 0.  Synchronises. */
 int ht_dump(ht_table* t, uint64_t* d_out, uint64_t cap, uint64_t* out_n,
             hipStream_t stream);
 
-/* Copy the raw storage to d_slots (device): the slot array (ht_stats_t
- * capacity words) followed by the stash (stash_slots words); empty slots
- * hold 0xFFFFFFFFFFFFFFFF.  `cap` is the room in words. */
+/* Infrastructure (structural tests).  Copy the raw storage to d_slots
+ * (device): the slot array (ht_stats_t capacity words) followed by the stash
+ * (stash_slots words); empty slots hold 0xFFFFFFFFFFFFFFFF.  `cap` is the
+ * room in words; HT_EINVAL when it is smaller than slots + stash.
+ * Asynchronous on `stream`. */
 int ht_dump_raw(ht_table* t, uint64_t* d_slots, uint64_t cap, hipStream_t stream);
 
-/* Remove every key (asynchronous). */
+/* Empty the table (Sec. 5: the table is initialised before each run of the
+ * find-or-insert benchmark): every slot, the stash, the overflow list and the
+ * counters are cleared; the hash constants are kept.  Asynchronous on
+ * `stream`; HT_EINVAL for a NULL table. */
 int ht_clear(ht_table* t, hipStream_t stream);
 
-/* Counters and geometry.  Synchronises. */
+/* Infrastructure.  Counters and geometry.  HT_EINVAL for a NULL out.
+ * Synchronises. */
 int ht_stats(ht_table* t, ht_stats_t* out, hipStream_t stream);
 
-/* Host-side hash of the table: the bucket index (bucketed) or slot index
+/* Infrastructure (structural tests).  Host-side hash of the table: the
+ * bucket index (bucketed) or slot index
  * (cuckoo) that h_j (0-based j < nhash) assigns to `key`.  For a vector table
  * `key` is a handle's hash bits (the handle shifted right by 34). */
 int ht_hash_index(const ht_table* t, uint64_t key, uint32_t j, uint64_t* out_index);
 
-/* Test mode (HT_FLAG_SCRIPTED_HASH): install `nkeys` scripted keys with
+/* Infrastructure.  Test mode (HT_FLAG_SCRIPTED_HASH), used to replay the
+ * exchange sequence of Fig. 2: install `nkeys` scripted keys with
  * their hash values; h_index is nkeys*nhash host words (row per key, each
  * < bucket count or slot count).  Keys not in the script hash to index 0. */
 int ht_set_scripted_hash(ht_table* t, const uint64_t* keys,
                          const uint64_t* h_index, uint32_t nkeys);
 
-/* Reserve scratch for batches up to max_batch keys (allocates). */
+/* Infrastructure (measurement).  Eviction chains of the table's Cuckoo
+ * find-or-puts since it was created or cleared, when it was created with
+ * HT_FLAG_CHAIN_STATS (else all zeros): out[0] = chains that ended in the
+ * stash (Sec. 4.1: after max_chain evictions), out[i] for 1 <= i < 63 =
+ * chains of exactly i exchanges, out[63] = chains of 63 or more.  `out` is a
+ * host array of 64 entries.  HT_EINVAL for a NULL table or out.
+ * Synchronises `stream`. */
+int ht_chain_histogram(ht_table* t, uint64_t* out, hipStream_t stream);
+
+/* Infrastructure.  Reserve scratch for batches up to max_batch keys
+ * (allocates, synchronises the device). */
 int ht_reserve(ht_table* t, uint64_t max_batch);
 
-/* Human-readable text of a status code. */
+/* Infrastructure.  Human-readable text of a status code (a static string;
+ * "unknown status" for codes not listed above). */
 const char* ht_strerror(int code);
 
-/* Text of the last error raised on this thread (HIP error string or
- * argument check), "" if none. */
+/* Infrastructure.  Text of the last error raised on this thread (HIP error
+ * string or argument check), "" if none. */
 const char* ht_last_error(void);
 
 /* ---- breadth-first exploration with a table as the visited set ---------- */
@@ -405,15 +461,20 @@ typedef struct {
 
 typedef struct ht_server ht_server;
 
+/* Infrastructure.  Fills *cfg with the defaults listed above (no-op for a
+ * NULL cfg). */
 void ht_server_config_default(ht_server_config* cfg);
 
-/* Serve `ntables` resident tables (the tables stay owned by the caller and
+/* Infrastructure (the serving engine has no counterpart in the paper; each
+ * request it runs is the find-or-put of Sec. 5 or the query of Sec. 4.1 and
+ * 4.2).  Serve `ntables` resident tables (the tables stay owned by the caller and
  * must outlive the server).  Allocates the staging budget, stream slots and
  * their events.  HT_EINVAL for scripted-hash tables or bad configs. */
 int ht_server_create(ht_table* const* tables, uint32_t ntables, const ht_server_config* cfg,
                      ht_server** out);
 
-/* Replay `nreq` requests: each is released at its arrival time, admitted in
+/* Serve a trace of find-or-put (Sec. 5) and query (Sec. 4.1, 4.2) requests.
+ * Replay `nreq` requests: each is released at its arrival time, admitted in
  * arrival order per table (FIFO) when its table is idle, a stream slot is
  * free and its staging fits, merged with admissible requests of other
  * tables into one launch group, and retired when the group's event
@@ -423,38 +484,45 @@ int ht_server_create(ht_table* const* tables, uint32_t ntables, const ht_server_
  * Cuckoo scratch for the largest request before starting the clock. */
 int ht_server_run(ht_server* s, ht_request* reqs, uint32_t nreq, ht_server_stats* stats);
 
-/* Free the server (synchronises the device); the tables are untouched. */
+/* Infrastructure.  Free the server (synchronises the device); the tables are
+ * untouched. */
 int ht_server_destroy(ht_server* s);
 
 /* ---- kernel timing (measurement aid) ------------------------------------ */
 
-/* Enable (on != 0) or disable per-kernel timing and reset the figures.  When
+/* Infrastructure (measurement).  Enable (on != 0) or disable per-kernel
+ * timing and reset the figures.  When
  * enabled, every kernel the library launches is bracketed by two HIP events
  * recorded on the stream it is launched on. */
 int ht_timing_enable(int on);
 
-/* JSON object {"kernel name": [launches, total milliseconds], ...} of the
+/* Infrastructure (measurement).  JSON object {"kernel name": [launches,
+ * total milliseconds], ...} of the
  * launches timed since ht_timing_enable; waits for their events.  HT_EINVAL
  * when buf is NULL or too small. */
 int ht_timing_report(char* buf, uint64_t len);
 
 /* ---- roofline probes: memory-system reference kernels ------------------- */
 
-/* Streaming copy of n 64-bit words d_src -> d_dst. */
+/* Infrastructure (measurement).  Streaming copy of n 64-bit words d_src ->
+ * d_dst. */
 int ht_probe_copy(const uint64_t* d_src, uint64_t* d_dst, uint64_t n, hipStream_t stream);
 
-/* n_access random reads of `line_bytes` (8, 64 or 128) from an array of
+/* Infrastructure (measurement).  n_access random reads of `line_bytes`
+ * (8, 64 or 128) from an array of
  * n_words 64-bit words; addresses come from a counter-based mixer seeded by
  * `seed`; the xor of the words read is stored to *d_sink. */
 int ht_probe_gather(const uint64_t* d_array, uint64_t n_words, uint64_t n_access,
                     uint32_t line_bytes, uint64_t seed, uint64_t* d_sink,
                     hipStream_t stream);
 
-/* n_access random 64-bit compare-and-swap operations on d_array. */
+/* Infrastructure (measurement).  n_access random 64-bit compare-and-swap
+ * operations on d_array. */
 int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access,
                  uint64_t seed, hipStream_t stream);
 
-/* The memory pattern of a find-or-put kernel, without the table logic: for
+/* Infrastructure (measurement).  The memory pattern of a find-or-put
+ * kernel, without the table logic: for
  * each of n_items keys (device), read the key, make `lines_per_item` random
  * 8-byte reads (on average; each costs a whole line at the memory) in
  * d_array (n_words 64-bit words, device), then with probability

@@ -2,7 +2,9 @@
 
 Argument marshalling only: every step of find-or-put and query runs in the
 HIP kernels of libht.so.  Torch tensors supply device memory, and the stream
-handle comes from ``torch.cuda.current_stream()`` unless one is given.  The
+handle comes from ``torch.cuda.current_stream()`` unless one is given; a
+given stream is made current while the call marshals its arguments, so key
+copies, flag allocations and kernels are ordered on it.  The
 functions ``ht_*`` mirror the C entry points one to one; ``Table`` wraps a
 handle with the same calls.
 
@@ -35,6 +37,8 @@ HT_FLAG_SCRIPTED_HASH = 1 << 2
 HT_FLAG_BUCKETED_PAPER_FULL = 1 << 3
 HT_FLAG_CUCKOO_SINGLE_PASS = 1 << 4
 HT_FLAG_BUCKETED_ONE_LANE = 1 << 5
+HT_FLAG_CHAIN_STATS = 1 << 6
+HT_FLAG_CUCKOO_LOOKAHEAD = 1 << 7
 
 EMPTY = (1 << 64) - 1
 
@@ -203,6 +207,7 @@ _PROTOS = {
     "ht_hash_index": (C.c_int, [_vp, _u64, _u32, C.POINTER(_u64)]),
     "ht_set_scripted_hash": (C.c_int, [_vp, C.POINTER(_u64), C.POINTER(_u64), _u32]),
     "ht_reserve": (C.c_int, [_vp, _u64]),
+    "ht_chain_histogram": (C.c_int, [_vp, C.POINTER(_u64), _vp]),
     "ht_strerror": (C.c_char_p, [C.c_int]),
     "ht_last_error": (C.c_char_p, []),
     "ht_bfs_explore": (C.c_int, [_vp, C.POINTER(HtBfsModel), _u64, _u32, C.POINTER(_u64), C.POINTER(_u64),
@@ -278,6 +283,20 @@ def _stream_handle(stream) -> int:
     return stream.cuda_stream
 
 
+def _on_stream(stream):
+    """Context in which torch's current stream is `stream` (a torch stream or
+    a raw handle), so that the copies and allocations of the marshalling are
+    ordered with the kernels launched there (and the caching allocator ties
+    the temporaries to that stream); a no-op for None."""
+    import contextlib
+    torch = _torch()
+    if stream is None:
+        return contextlib.nullcontext()
+    if isinstance(stream, int):
+        stream = torch.cuda.ExternalStream(stream)
+    return torch.cuda.stream(stream)
+
+
 def _key_tensor(keys, device=None):
     """Device tensor of 64-bit keys (int64 view of uint64 bits)."""
     torch = _torch()
@@ -340,12 +359,14 @@ def _count(k, w: int) -> int:
 
 def ht_find_or_put(h: int, keys, out=None, stream=None, key_words: int = 1):
     """keys: n 64-bit keys, or for a vector table n rows of key_words words
-    (any shape with n * key_words elements, row-major)."""
-    k = _key_tensor(keys)
-    n = _count(k, key_words)
-    o = _out_tensor(out, n, k)
-    _check(load().ht_find_or_put(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(stream)),
-           "ht_find_or_put")
+    (any shape with n * key_words elements, row-major).  With `stream`, the
+    key copy, the flag allocation and the kernels all run on that stream."""
+    with _on_stream(stream):
+        k = _key_tensor(keys)
+        n = _count(k, key_words)
+        o = _out_tensor(out, n, k)
+        _check(load().ht_find_or_put(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(None)),
+               "ht_find_or_put")
     return o
 
 
@@ -353,10 +374,11 @@ ht_insert = ht_find_or_put
 
 
 def ht_query(h: int, keys, out=None, stream=None, key_words: int = 1):
-    k = _key_tensor(keys)
-    n = _count(k, key_words)
-    o = _out_tensor(out, n, k)
-    _check(load().ht_query(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(stream)), "ht_query")
+    with _on_stream(stream):
+        k = _key_tensor(keys)
+        n = _count(k, key_words)
+        o = _out_tensor(out, n, k)
+        _check(load().ht_query(h, k.data_ptr(), n, o.data_ptr(), _stream_handle(None)), "ht_query")
     return o
 
 
@@ -377,15 +399,17 @@ def _multi_args(handles, keys_list, outs, key_words):
 
 
 def ht_find_or_put_multi(handles: Sequence[int], keys_list, outs=None, stream=None, key_words=None):
-    ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
-    _check(load().ht_find_or_put_multi(th, kp, nn, op, len(handles), _stream_handle(stream)),
-           "ht_find_or_put_multi")
+    with _on_stream(stream):
+        ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
+        _check(load().ht_find_or_put_multi(th, kp, nn, op, len(handles), _stream_handle(None)),
+               "ht_find_or_put_multi")
     return os_
 
 
 def ht_query_multi(handles: Sequence[int], keys_list, outs=None, stream=None, key_words=None):
-    ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
-    _check(load().ht_query_multi(th, kp, nn, op, len(handles), _stream_handle(stream)), "ht_query_multi")
+    with _on_stream(stream):
+        ks, os_, th, kp, nn, op = _multi_args(handles, keys_list, outs, key_words)
+        _check(load().ht_query_multi(th, kp, nn, op, len(handles), _stream_handle(None)), "ht_query_multi")
     return os_
 
 
@@ -445,20 +469,22 @@ def ht_dump(h: int, stream=None, key_words: int = 1):
     """Members as an int64 GPU tensor (uint64 bits), any order; for a vector
     table an (n, key_words) tensor."""
     torch = _torch()
-    n = ht_size(h, stream)
-    buf = torch.empty((max(n, 1), key_words), dtype=torch.int64, device="cuda")
-    got = _u64()
-    _check(load().ht_dump(h, buf.data_ptr(), buf.shape[0], C.byref(got), _stream_handle(stream)), "ht_dump")
+    with _on_stream(stream):
+        n = ht_size(h)
+        buf = torch.empty((max(n, 1), key_words), dtype=torch.int64, device="cuda")
+        got = _u64()
+        _check(load().ht_dump(h, buf.data_ptr(), buf.shape[0], C.byref(got), _stream_handle(None)), "ht_dump")
     buf = buf[: got.value]
     return buf.reshape(-1) if key_words == 1 else buf
 
 
 def ht_dump_raw(h: int, stream=None):
     torch = _torch()
-    st = ht_stats(h, stream)
-    cap = st["capacity"] + st["stash_slots"]
-    buf = torch.empty(cap, dtype=torch.int64, device="cuda")
-    _check(load().ht_dump_raw(h, buf.data_ptr(), cap, _stream_handle(stream)), "ht_dump_raw")
+    with _on_stream(stream):
+        st = ht_stats(h)
+        cap = st["capacity"] + st["stash_slots"]
+        buf = torch.empty(cap, dtype=torch.int64, device="cuda")
+        _check(load().ht_dump_raw(h, buf.data_ptr(), cap, _stream_handle(None)), "ht_dump_raw")
     return buf
 
 
@@ -481,6 +507,28 @@ def ht_set_scripted_hash(h: int, script: dict, nhash: int) -> None:
         raise ValueError("each scripted key needs nhash values")
     ha = (_u64 * max(len(flat), 1))(*flat)
     _check(load().ht_set_scripted_hash(h, ka, ha, n), "ht_set_scripted_hash")
+
+
+def ht_chain_histogram(h: int, stream=None) -> dict:
+    """Eviction-chain histogram (tables created with HT_FLAG_CHAIN_STATS):
+    {"stash": chains that ended in the stash, "counts": [chains of i
+    exchanges for i = 0..63, the last counting 63 or more], "mean", "p99",
+    "max": over chains that found a slot}."""
+    a = (_u64 * 64)()
+    _check(load().ht_chain_histogram(h, a, _stream_handle(stream)), "ht_chain_histogram")
+    counts = [int(a[i]) for i in range(64)]
+    stash, counts[0] = counts[0], 0
+    total = sum(counts)
+    mean = p99 = mx = None
+    if total:
+        mean = round(sum(i * c for i, c in enumerate(counts)) / total, 3)
+        acc = 0
+        for i, c in enumerate(counts):
+            acc += c
+            if p99 is None and acc >= 0.99 * total:
+                p99 = i
+        mx = max(i for i, c in enumerate(counts) if c)
+    return {"stash": stash, "counts": counts, "chains": total, "mean": mean, "p99": p99, "max": mx}
 
 
 def ht_reserve(h: int, max_batch: int) -> None:

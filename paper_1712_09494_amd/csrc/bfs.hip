@@ -324,7 +324,8 @@ __global__ __launch_bounds__(kBlock) void bfs_cuckoo_evict_kernel(DevTable t, ui
                             __HIP_MEMORY_SCOPE_AGENT);
       __hip_atomic_fetch_add(&cnt[i], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       uint64_t y = k;
-      if (!cuckoo_chain<false>(t, y, hidx<false>(t, y, 0), nevict)) stash_put(t, y);
+      uint32_t steps = 0;
+      if (!cuckoo_chain<false>(t, y, hidx<false>(t, y, 0), nevict, steps)) stash_put(t, y);
       ++nnew;
     }
   }

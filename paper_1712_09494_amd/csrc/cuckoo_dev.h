@@ -274,13 +274,24 @@ __global__ __launch_bounds__(kBlock) void cuckoo_probe_kernel(DevTable t, const 
 
 // Eviction chain of Sec. 4.1 for key x starting at slot index `slot` (which
 // is h_j0(x)).  Returns true when the chain ended on an empty slot; on false
-// `x` holds the key left without a slot.
+// `x` holds the key left without a slot.  `steps` counts the exchanges.
+//
+// With the lookahead flag (kFlagLookahead), a key y evicted from h_a(y)
+// first reads its later candidates h_{a+1}(y), ..., h_c(y) (one load each,
+// issued together) and compare-and-swaps itself into the lowest-numbered one
+// it saw empty; only when none is empty (or every such compare-and-swap
+// loses) does the chain go on by exchange into the next candidate.  Placing
+// y at h_j this way keeps the early-exit invariant of the lookups: h_1..h_a
+// are taken (y sat at h_a, which the evicting key now holds) and
+// h_{a+1}..h_{j-1} were seen taken, and slots never empty again.
 template <bool SCRIPTED>
 __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uint64_t slot,
-                                             unsigned long long& nevict) {
+                                             unsigned long long& nevict, uint32_t& steps) {
   const uint32_t c = t.nhash;
+  const bool look = (t.flags & kFlagLookahead) != 0;
   for (uint32_t step = 0;; ++step) {
     const uint64_t old = exch64(&t.slots[slot], x);
+    ++steps;
     if (old == kEmpty) return true;
     x = old;
     ++nevict;
@@ -293,6 +304,13 @@ __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uin
       h[j] = hidx<SCRIPTED>(t, x, j);
       if (h[j] == slot) a = (int)j;
     }
+    if (look && a + 1 < (int)c) {
+      uint64_t v[kMaxHash];
+      for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) v[j] = h[j] != slot ? t.slots[h[j]] : 0;
+      for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) {
+        if (h[j] != slot && v[j] == kEmpty && cas64(&t.slots[h[j]], kEmpty, x) == kEmpty) return true;
+      }
+    }
     uint32_t nj = (uint32_t)(a + 1) % c;
     uint32_t tries = 0;
     while (h[nj] == slot && tries < c) {
@@ -302,6 +320,14 @@ __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uin
     if (h[nj] == slot) return false;   // no other slot for x
     slot = h[nj];
   }
+}
+
+// Chain-length histogram (measurement flag): one atomic per chain on one of
+// kSpread copies.
+__device__ __forceinline__ void chain_record(const DevTable& t, uint32_t steps, bool placed, uint64_t wave) {
+  if (!(t.flags & kFlagChainStats)) return;
+  const uint32_t bin = placed ? (steps < (uint32_t)kChainBins ? steps : (uint32_t)kChainBins - 1) : 0u;
+  add_agent(&t.ctr->chain_hist[(wave % kSpread) * kChainBins + bin], 1ull);
 }
 
 // Kernel 2: evict.  The keys kernel 1 listed are deduplicated in the
@@ -329,8 +355,10 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
     s.wmeta[begin + e] = winner ? p : ~0ull;
     if (!winner) continue;
     uint64_t y = k;
-    if (!cuckoo_chain<SCRIPTED>(t, y, hidx<SCRIPTED>(t, y, 0), nevict))
-      stash_put(t, y);                   // y may be another key than the winner's
+    uint32_t steps = 0;
+    const bool placed = cuckoo_chain<SCRIPTED>(t, y, hidx<SCRIPTED>(t, y, 0), nevict, steps);
+    if (!placed) stash_put(t, y);        // y may be another key than the winner's
+    chain_record(t, steps, placed, wave);
     ++nnew;
   }
 }

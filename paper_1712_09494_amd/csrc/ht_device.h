@@ -22,6 +22,11 @@ constexpr int kSpread = 16;          // hot counters are spread over 16 lines
 constexpr int kLineWords = 16;       // 128-byte line = 16 words
 constexpr int kMaxHash = 8;
 constexpr int kArenaBits = 34;       // vector tables: arena index bits of a handle
+constexpr int kChainBins = 64;       // eviction-chain histogram bins
+
+// Table flags the kernels read (same values as the HT_FLAG_* of the C ABI).
+constexpr uint32_t kFlagChainStats = 1u << 6;
+constexpr uint32_t kFlagLookahead = 1u << 7;
 
 // Hash family: h_j(k) = floor(mix64(k ^ s_j) * range / 2^64).
 // mix64 is the splitmix64 finalizer (Steele, Lea & Flood 2014), a bijection
@@ -56,6 +61,10 @@ struct Counters {
   // vector tables: entries taken in each of the kSpread arena ranges (may
   // exceed the range size; the excess was never handed out)
   unsigned long long arena_next[kSpread * kLineWords];
+  // Cuckoo eviction chains by number of exchanges (bin 0: chains that ended
+  // in the stash; 1..kChainBins-1: exchanges, the last bin also counting
+  // longer ones); kSpread copies, filled only under the chain-stats flag
+  unsigned long long chain_hist[kSpread * kChainBins];
 };
 
 // Scripted hash row (test mode): key and its c hash values.

@@ -284,8 +284,10 @@ int validate_config(const ht_config* c) {
     return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS |
-                             HT_FLAG_BUCKETED_ONE_LANE))
+                             HT_FLAG_BUCKETED_ONE_LANE | HT_FLAG_CHAIN_STATS | HT_FLAG_CUCKOO_LOOKAHEAD))
     return fail(HT_EINVAL, "unknown flag bits");
+  if ((c->flags & HT_FLAG_CUCKOO_LOOKAHEAD) && (c->flags & HT_FLAG_CUCKOO_PAPER_ORDER))
+    return fail(HT_EINVAL, "the lookahead flag changes the paper-order insertion; use one of them");
   if ((c->flags & HT_FLAG_BUCKETED_ONE_LANE) && (c->kind != HT_BUCKETED || c->key_words > 1))
     return fail(HT_EINVAL, "the one-lane flag is for bucketed tables of single-word keys");
   if ((c->flags & HT_FLAG_CUCKOO_SINGLE_PASS) && (c->kind != HT_CUCKOO || c->key_words > 1))
@@ -887,25 +889,46 @@ int ht_clear(ht_table* t, hipStream_t s) {
 int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t s) {
   int rc = check_table(t);
   if (rc) return rc;
+  if (new_capacity > (1ull << 40)) return fail(HT_EINVAL, "capacity above 2^40 slots");
+  if (t->cfg.key_words > 1 && new_capacity &&
+      new_capacity + t->dev.stash_slots + t->dev.overflow_slots + 64 >= (1ull << (kArenaBits - 1)))
+    return fail(HT_EINVAL, "vector table capacity above 2^33 entries");
+  // every member (slots, stash, overflow list, the all-ones key) to a device buffer
   uint64_t* buf = nullptr;
   uint64_t n = 0;
   rc = dump_members(t, &buf, &n, s);
   if (rc) return rc;
-  if (new_capacity && new_capacity != t->cfg.capacity) {
-    HT_HIP(hipStreamSynchronize(s));
-    free_storage(t);
+  HT_HIP(hipStreamSynchronize(s));
+  // The old storage stays untouched until the members are all placed in the
+  // new one: allocate first, and on any failure put the old table back.
+  const ht_config old_cfg = t->cfg, old_user = t->user_cfg;
+  const uint64_t old_nslots = t->nslots;
+  const DevTable old_dev = t->dev;
+  void* const old_storage = t->storage;
+  unsigned long long* const old_misc = t->misc;
+  auto restore = [&]() {
+    t->cfg = old_cfg;
+    t->user_cfg = old_user;
+    t->nslots = old_nslots;
+    t->dev = old_dev;
+    t->storage = old_storage;
+    t->misc = old_misc;
+  };
+  if (new_capacity) {
     t->cfg = t->user_cfg;
     t->cfg.capacity = new_capacity;
     t->user_cfg.capacity = new_capacity;
     setup_geometry(t);
-    rc = alloc_storage(t);
-    if (rc) {
-      (void)hipFree(buf);
-      return rc;
-    }
+  }
+  t->storage = nullptr;
+  rc = alloc_storage(t);
+  if (rc) {
+    restore();
+    (void)hipFree(buf);
+    return rc;
   }
   for (int attempt = 0; attempt < 8; ++attempt) {
-    draw_constants(t);
+    draw_constants(t);          // the hash constants live in t->dev, so a restore keeps the old ones
     rc = clear_async(t, s);
     if (!rc && n) rc = do_find_or_put(t, buf, n, nullptr, s);
     if (rc) break;
@@ -913,11 +936,18 @@ int ht_rebuild(ht_table* t, uint64_t new_capacity, hipStream_t s) {
     rc = read_counters(t, &h, s);
     if (rc) break;
     if (!h.overflow_count && !h.lost) break;
-    rc = fail(HT_EFULL, "rebuild could not place every key; grow the table");
+    rc = fail(HT_EFULL, "rebuild could not place every key in slots and stash; the table is unchanged "
+                        "(grow it)");
   }
   (void)hipStreamSynchronize(s);
   (void)hipFree(buf);
-  return rc;
+  if (rc) {
+    (void)hipFree(t->storage);
+    restore();
+    return rc;
+  }
+  (void)hipFree(old_storage);
+  return HT_OK;
 }
 
 int ht_stats(ht_table* t, ht_stats_t* out, hipStream_t s) {
@@ -978,6 +1008,21 @@ int ht_set_scripted_hash(ht_table* t, const uint64_t* keys, const uint64_t* h_in
     HT_HIP(hipMemcpy(t->script, rows.data(), sizeof(ScriptRow) * nkeys, hipMemcpyHostToDevice));
   }
   t->nscript = nkeys;
+  return HT_OK;
+}
+
+int ht_chain_histogram(ht_table* t, uint64_t* out, hipStream_t s) {
+  int rc = check_table(t);
+  if (rc) return rc;
+  if (!out) return fail(HT_EINVAL, "out is NULL");
+  Counters h;
+  rc = read_counters(t, &h, s);
+  if (rc) return rc;
+  for (int b = 0; b < kChainBins; ++b) {
+    uint64_t v = 0;
+    for (int i = 0; i < kSpread; ++i) v += h.chain_hist[i * kChainBins + b];
+    out[b] = v;
+  }
   return HT_OK;
 }
 

@@ -104,3 +104,33 @@ def test_bfs_model_packing():
         assert [pm.sync_p_edge[a][s] for s in range(16)] == [x[0] if x else -1 for x in pe]
     lib = b.load()
     assert lib.ht_bfs_explore(None, C.byref(pm), 0, 3, None, None, None, None) == b.HT_EINVAL
+
+
+def header_docs():
+    """{function: the comment block right before its declaration}."""
+    src = open(os.path.join(ROOT, "include", "ht.h")).read()
+    out = {}
+    for m in re.finditer(r"/\*((?:(?!\*/).)*)\*/\s*\n((?:[A-Za-z_][\w\s\*]*?\b(ht_[a-z_0-9]+)\s*\([^;]*;\s*\n?)+)",
+                         src, flags=re.S):
+        for name in re.findall(r"\b(ht_[a-z_0-9]+)\s*\(", m.group(2)):
+            out.setdefault(name, m.group(1))
+    return out
+
+
+def test_every_entry_point_cites_its_passage_or_says_infrastructure():
+    """Each declaration in ht.h follows a comment that cites the passage of
+    the paper defining the operation (Sec. / Fig.), refers to the call it
+    equals, or marks it as infrastructure."""
+    docs = header_docs()
+    names = header_functions()
+    missing = [n for n in names if n not in docs]
+    assert not missing, missing
+    for n in names:
+        d = docs[n]
+        assert re.search(r"Sec\. \d|Fig\. \d|Infrastructure|Same as ht_", d), n
+    # the calls whose defining passage the paper gives
+    for n in ("ht_create", "ht_find_or_put", "ht_query", "ht_sync_status", "ht_rebuild", "ht_size", "ht_dump",
+              "ht_clear", "ht_find_or_put_multi", "ht_bfs_explore"):
+        assert re.search(r"Sec\. \d", docs[n]), n
+    for n in ("ht_destroy", "ht_stats", "ht_dump_raw", "ht_strerror", "ht_create_simple", "ht_last_error"):
+        assert "Infrastructure" in docs[n], n

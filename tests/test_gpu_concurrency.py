@@ -66,3 +66,31 @@ def test_threads_on_their_own_tables_and_streams():
                 check_query_r1(half, o.query(qs[i]), f"thread {i} mid-run queries")
         check_query_r1(found, o.query(qs[i]), f"thread {i} queries")
         assert size == o.size, i
+
+
+@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+@pytest.mark.parametrize("raw_handle", [False, True])
+def test_stream_argument_without_entering_the_stream(kind, kw, raw_handle):
+    """stream= given without making it current: the binding copies the
+    numpy keys and allocates the flags on that stream, ordered with the
+    kernels, while torch's current stream is busy with other work."""
+    s = torch.cuda.Stream()
+    arg = s.cuda_stream if raw_handle else s
+    seq = inputs.random_sequence(8 * 50000, 300000, seed=77)
+    q = inputs.query_sequence(40000, 300000, 0.5, seed=77, query_seed=78)
+    big = torch.randn(4096, 4096, device="cuda")
+    with b.Table(kind, capacity=1 << 20, nhash=3, **kw) as t:
+        t.clear(stream=arg)
+        o = Oracle()
+        flags = []
+        for j in range(8):
+            big = big @ big * 1e-3                 # keeps torch's current stream busy
+            flags.append(t.find_or_put(seq[j * 50000:(j + 1) * 50000], stream=arg))
+        found = t.query(q, stream=arg)
+        s.synchronize()
+        for j in range(8):
+            part = seq[j * 50000:(j + 1) * 50000]
+            check_flags_r2(part, flags[j].cpu().numpy(), o.find_or_put(part), f"batch {j}")
+        check_query_r1(found.cpu().numpy(), o.query(q), "queries")
+        assert t.size(stream=arg) == o.size
+    torch.cuda.synchronize()

@@ -33,8 +33,9 @@ DESIGNS = {
     "bkt8_lane": dict(kind="bucketed", bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
     "bkt64_lane": dict(kind="bucketed", bucket_slots=64, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
     "cuckoo_lds64k": dict(kind="cuckoo", lds_bytes=65536),
+    "cuckoo_look": dict(kind="cuckoo", flags=b.HT_FLAG_CUCKOO_LOOKAHEAD),
 }
-MAIN = ["bkt16", "bkt8", "bkt16_cached", "cuckoo", "cuckoo_paper"]
+MAIN = ["bkt16", "bkt8", "bkt16_cached", "cuckoo", "cuckoo_paper", "cuckoo_look"]
 MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4", "bkt8_lane"]
 
 

@@ -68,7 +68,7 @@ def test_bucketed_prefix_and_spill_order(B, lf, flags):
     t.close()
 
 
-@pytest.mark.parametrize("flags", [0, b.HT_FLAG_CUCKOO_PAPER_ORDER])
+@pytest.mark.parametrize("flags", [0, b.HT_FLAG_CUCKOO_PAPER_ORDER, b.HT_FLAG_CUCKOO_LOOKAHEAD])
 def test_cuckoo_key_in_candidate_slot_or_stash(flags):
     n = 30000
     t = b.Table("cuckoo", capacity=int(n / 0.85), nhash=3, flags=flags)
@@ -94,7 +94,7 @@ def test_cuckoo_key_in_candidate_slot_or_stash(flags):
     t.close()
 
 
-@pytest.mark.parametrize("flags", [0, b.HT_FLAG_CUCKOO_PAPER_ORDER])
+@pytest.mark.parametrize("flags", [0, b.HT_FLAG_CUCKOO_PAPER_ORDER, b.HT_FLAG_CUCKOO_LOOKAHEAD])
 def test_cuckoo_coinciding_indices_keep_full_lookup(flags):
     """A key with h_1 == h_3 (c = 4) evicted from that slot skips h_2 and moves
     to h_4 (next hash after the last index mapping to its slot, Sec. 4.1),
@@ -169,6 +169,78 @@ def test_stash_overflow_and_rebuild(kind, B):
     check_flags_r2(more, b.u64(t.find_or_put(dev(more)).to(torch.int64)).astype(np.uint8),
                    o.find_or_put(more), "after rebuild")
     t.close()
+
+
+@pytest.mark.parametrize("kind,B", [("bucketed", 16), ("cuckoo", 0)])
+def test_rebuild_that_fails_leaves_the_table_as_it_was(kind, B):
+    """Sec. 4.1's rebuild may fail: a growth the device cannot allocate
+    (hipMalloc returns an error) gives HT_ENOMEM, and a rebuild that cannot
+    place every member in slots and stash gives HT_EFULL.  Either way the
+    table keeps every member (overflow list included), its hash constants and
+    its answers; a rebuild that can succeed afterwards does."""
+    kw = dict(bucket_slots=B, flags=b.HT_FLAG_BUCKETED_PAPER_FULL) if B else {}
+    t = b.Table(kind, capacity=64, nhash=1, stash_slots=16, overflow_slots=4096, **kw)
+    keys = inputs.uniform_keys(500, seed=5)
+    t.find_or_put(dev(keys))
+    before = t.stats()
+    dump0 = np.sort(b.u64(t.dump()))
+    raw0 = b.u64(t.dump_raw())
+    assert before["overflow_count"] > 0 and before["lost"] == 0 and t.size() == 500
+
+    def unchanged(what):
+        assert t.sync_status() == b.HT_EFULL, what
+        st = t.stats()
+        for k in ("size", "capacity", "stash_count", "overflow_count", "lost", "seed"):
+            assert st[k] == before[k], (what, k)
+        assert np.array_equal(np.sort(b.u64(t.dump())), dump0), what
+        assert np.array_equal(b.u64(t.dump_raw()), raw0), what
+        assert b.u64(t.query(dev(keys)).to(torch.int64)).all(), what
+        absent = inputs.key_of_index(np.arange(10 ** 6, 10 ** 6 + 300), seed=5)   # indices never inserted
+        assert not b.u64(t.query(dev(absent)).to(torch.int64)).any(), what
+
+    with pytest.raises(b.HtError) as e:
+        t.rebuild(new_capacity=1 << 39)          # 4 TiB of slots: the allocation fails
+    assert e.value.code == b.HT_ENOMEM
+    unchanged("after the failed growth")
+    with pytest.raises(b.HtError) as e:
+        t.rebuild()                              # 500 keys cannot fit 64 slots and 16 stash slots
+    assert e.value.code == b.HT_EFULL
+    unchanged("after the failed rebuild in place")
+    with pytest.raises(b.HtError) as e:
+        t.rebuild(new_capacity=(1 << 40) + 1)
+    assert e.value.code == b.HT_EINVAL
+    unchanged("after the rejected capacity")
+    t.rebuild(new_capacity=1 << 16)            # c = 1: room for 500 keys with few collisions
+    assert t.sync_status() == b.HT_OK and t.size() == 500
+    check_dump_r3(b.u64(t.dump()), np.unique(keys), t.size(), kind)
+    t.close()
+
+
+@pytest.mark.parametrize("lf", [0.7, 0.85])
+def test_chain_histogram_accounts_for_every_eviction(lf):
+    """With the chain-stats flag every eviction chain of the plain Sec. 4.1
+    chain is counted once: a chain placed after k exchanges evicted k - 1
+    keys, one that reached the stash evicted max_chain, so the histogram sums
+    to the table's eviction counter; with the lookahead flag the chains are
+    counted too and the table stays exact."""
+    n = 200000
+    keys = inputs.uniform_keys(n, seed=31)
+    for flags in (0, b.HT_FLAG_CUCKOO_LOOKAHEAD):
+        t = b.Table("cuckoo", capacity=int(n / lf), nhash=3, max_chain=40, stash_slots=4096,
+                    flags=flags | b.HT_FLAG_CHAIN_STATS)
+        for s0 in range(0, n, 1 << 14):
+            t.find_or_put(dev(keys[s0:s0 + (1 << 14)]))
+        h = b.ht_chain_histogram(t.handle)
+        st = t.stats()
+        assert h["chains"] > 0 and h["counts"][0] == 0 and t.size() == n
+        if flags == 0:
+            assert h["counts"][63] == 0
+            assert sum((i - 1) * c for i, c in enumerate(h["counts"]) if i) + 40 * h["stash"] == st["evictions"]
+        t.clear()
+        assert b.ht_chain_histogram(t.handle)["chains"] == 0
+        t.close()
+    with pytest.raises(b.HtError):
+        b.Table("cuckoo", capacity=1024, flags=b.HT_FLAG_CUCKOO_LOOKAHEAD | b.HT_FLAG_CUCKOO_PAPER_ORDER)
 
 
 def test_large_capacity_no_spill():

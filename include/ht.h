@@ -201,6 +201,22 @@ int ht_destroy(ht_table* t);
 int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n,
                    uint8_t* d_out_is_new, hipStream_t stream);
 
+/* For callers that cannot allocate (code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation): ht_find_or_put that
+ * allocates nothing.  Same kernels and results (Sec. 5 find-or-put); the
+ * scratch of the Cuckoo insertion (deduplication set, listed keys, per-wave
+ * counts) is a static device array of 8.06 MiB held by each device the
+ * library runs on until the process ends, instead of the table's own
+ * scratch.  Limits: n <= 262144 keys (HT_EINVAL above), tables of
+ * single-word keys only (HT_EINVAL for key_words > 1), and the table's device
+ * must be the current device (HT_EINVAL otherwise).  Bucketed tables and
+ * HT_FLAG_CUCKOO_SINGLE_PASS use no scratch.  Every call on one device shares
+ * that device's array: calls that may overlap on one device (different
+ * streams, different host threads, different tables) race and must be
+ * ordered by the caller.  Creates no HIP events and calls no memset. */
+int ht_find_or_put_noalloc(ht_table* t, const uint64_t* d_keys, uint64_t n,
+                           uint8_t* d_out_is_new, hipStream_t stream);
+
 /* Same as ht_find_or_put. */
 int ht_insert(ht_table* t, const uint64_t* d_keys, uint64_t n,
               uint8_t* d_out_is_new, hipStream_t stream);

@@ -189,6 +189,7 @@ _PROTOS = {
     "ht_destroy": (C.c_int, [_vp]),
     "ht_find_or_put": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_insert": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
+    "ht_find_or_put_noalloc": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_query": (C.c_int, [_vp, _vp, _u64, _vp, _vp]),
     "ht_find_or_put_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
     "ht_query_multi": (C.c_int, [C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_u64), C.POINTER(_vp), _u32, _vp]),
@@ -371,6 +372,22 @@ def ht_find_or_put(h: int, keys, out=None, stream=None, key_words: int = 1):
 
 
 ht_insert = ht_find_or_put
+
+
+def ht_find_or_put_noalloc(h: int, keys, out, stream=None):
+    """The allocation-free find-or-put (at most 262144 single-word keys).
+    ``keys`` and ``out`` must already be device tensors (int64/uint64 keys,
+    uint8 flags with room for every key): nothing is copied or allocated."""
+    torch = _torch()
+    if not (isinstance(keys, torch.Tensor) and keys.is_cuda and keys.is_contiguous()
+            and keys.dtype in (torch.int64, torch.uint64)):
+        raise TypeError("keys must be a contiguous int64/uint64 GPU tensor")
+    if not (isinstance(out, torch.Tensor) and out.is_cuda and out.is_contiguous() and out.dtype == torch.uint8
+            and out.numel() >= keys.numel()):
+        raise TypeError("out must be a contiguous uint8 GPU tensor with room for every key")
+    _check(load().ht_find_or_put_noalloc(h, keys.data_ptr(), keys.numel(), out.data_ptr(), _stream_handle(stream)),
+           "ht_find_or_put_noalloc")
+    return out
 
 
 def ht_query(h: int, keys, out=None, stream=None, key_words: int = 1):

@@ -62,7 +62,12 @@ int check_table(const ht_table* t);
 int reserve_scratch(ht_table* t, uint64_t n);
 ht::DevTable launch_view(const ht_table* t);
 ht::CuckooScratch scratch_view(const ht_table* t, uint64_t n);   // per_wave left for the caller
-int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s);
+// `fixed`: scratch provided by the caller (Cuckoo tables of single-word keys;
+// per_wave is set here), instead of the table's own.
+int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s,
+                   const ht::CuckooScratch* fixed = nullptr);
+uint64_t pow2_at_least(uint64_t x);
+extern thread_local bool g_quiet;   // set: launches create no timing events
 int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s);
 
 }  // namespace ht_rt

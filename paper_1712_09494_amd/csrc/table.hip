@@ -110,11 +110,15 @@ bool g_timing = false;
 std::vector<PendingTiming> g_pending;
 std::map<std::string, std::pair<uint64_t, double>> g_acc;   // name -> (launches, total ms)
 
+// Set while the allocation-free call runs: its launches create no events.
+thread_local bool g_quiet = false;
+
 struct KernelTimer {
   PendingTiming p{};
   bool on = false;
   hipStream_t s;
   KernelTimer(const char* name, hipStream_t st) : s(st) {
+    if (g_quiet) return;
     std::lock_guard<std::mutex> lk(g_tmu);
     if (!g_timing) return;
     p.name = name;
@@ -434,8 +438,12 @@ static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_
   return HT_OK;
 }
 
-int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s) {
-  if (t->cfg.key_words > 1) return vec_find_or_put(t, keys, n, out, s);
+int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s,
+                   const CuckooScratch* fixed) {
+  if (t->cfg.key_words > 1) {
+    if (fixed) return fail(HT_EINVAL, "state-vector tables take no caller scratch");
+    return vec_find_or_put(t, keys, n, out, s);
+  }
   const DevTable d = launch_view(t);
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
@@ -460,12 +468,17 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     HT_HIP(cuckoo_single_pass(d, keys, n, out, (uint32_t)blocks, scripted, s));
     return HT_OK;
   }
-  int rc = reserve_scratch(t, n);
-  if (rc != HT_OK) return rc;
+  CuckooScratch sc{};
+  if (fixed) {
+    sc = *fixed;                  // scratch the caller provides (the allocation-free call)
+  } else {
+    int rc = reserve_scratch(t, n);
+    if (rc != HT_OK) return rc;
+    sc = scratch_view(t, n);
+  }
   const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
   const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
   const uint64_t nwaves = blocks * 4;
-  CuckooScratch sc = scratch_view(t, n);
   sc.per_wave = (n + nwaves - 1) / nwaves;
   const bool paper = (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
   {

@@ -274,8 +274,8 @@ def main():
         cas = cas_probe_rate(b, torch, dev, stream, cap)
         line = line_probe_rate(b, torch, dev, stream, cap)
         for name, rl in rls.items():
-            atomics = measured_counter(name, "ea_atomics")
-            fetch_kib = measured_counter(name, "fetch_kib")
+            atomics = measured_counter(name, "TCC_EA0_ATOMIC_sum")
+            fetch_kib = measured_counter(name, "FETCH_SIZE")
             scale = counter_scale("fetch_scale")
             if None in (atomics, fetch_kib, scale):
                 continue
@@ -562,15 +562,21 @@ def kernel_rooflines(per_kernel, args, d, cap, new_per_batch):
 def mix_probe(b, torch, dev, stream, keys, words, lines, cas, kernel_ms, reps=5):
     """The mixed memory-pattern probe on the kernel's own keys over an array
     of the table's size (emptied first), with the kernel's lines and
-    compare-and-swaps per key: its time against the kernel's."""
-    arr = torch.full((words,), -1, dtype=torch.int64, device=dev)
-    flags = torch.empty(keys.numel(), dtype=torch.uint8, device=dev)
-    sec = _timed(torch, stream, lambda: b.ht_probe_mix(keys, flags, arr, lines, cas, 11), reps=reps)
-    del arr, flags
-    probe_ms = sec * 1e3
-    return {"probe_ms": round(probe_ms, 5), "lines_per_key": round(lines, 4), "cas_per_key": round(cas, 4),
-            "frac_of_mix": round(probe_ms / kernel_ms, 3),
-            "array_MiB": round(words * 8 / 2 ** 20, 1)}
+    compare-and-swaps per key, twice: with each compare-and-swap in a line of
+    its own, and in the line just read (the table kernels' pattern); their
+    times against the kernel's (frac_of_mix uses the same-line form)."""
+    res = {"lines_per_key": round(lines, 4), "cas_per_key": round(cas, 4), "array_MiB": round(words * 8 / 2 ** 20, 1)}
+    for name, same in (("other_line", False), ("same_line", True)):
+        arr = torch.full((words,), -1, dtype=torch.int64, device=dev)
+        flags = torch.empty(keys.numel(), dtype=torch.uint8, device=dev)
+        sec = _timed(torch, stream, lambda: b.ht_probe_mix(keys, flags, arr, lines, cas, 11, same_line=same),
+                     reps=reps)
+        del arr, flags
+        res[f"probe_ms_{name}"] = round(sec * 1e3, 5)
+    res["probe_ms"] = res["probe_ms_same_line"]
+    res["frac_of_mix"] = round(res["probe_ms"] / kernel_ms, 3)
+    res["frac_of_mix_other_line"] = round(res["probe_ms_other_line"] / kernel_ms, 3)
+    return res
 
 
 def evict_profile(b, torch, cap, keys, out, n, batch, flags=0):
@@ -605,48 +611,37 @@ def evict_profile(b, torch, cap, keys, out, n, batch, flags=0):
             "stash": int(st["stash_count"]), "chains": hist}
 
 
-# Sources that define or launch the kernels of the counted workload (the
-# single-table find-or-put kernels of both designs and what they include).
-COUNTED_SOURCES = ("ht_device.h", "bucketed_dev.h", "bucketed.hip", "cuckoo_dev.h", "cuckoo.hip", "runtime.h",
-                   "table.hip", "util.hip")
-
-
 def kernel_source_hash() -> str:
-    """sha256 over the HIP sources of the counted kernels, to tell whether
-    committed counters are current."""
-    import hashlib
-    h = hashlib.sha256()
-    csrc = os.path.join(ROOT, "paper_1712_09494_amd", "csrc")
-    for name in sorted(COUNTED_SOURCES):
-        h.update(name.encode())
-        with open(os.path.join(csrc, name), "rb") as f:
-            h.update(f.read())
-    return h.hexdigest()
+    """sha256 over the sources of the counted kernels (the value the committed
+    counter summary records), to tell whether those counters are current."""
+    from paper_1712_09494_amd import profile_summary
+    return profile_summary.source_hash()
 
 
-def measured_counter(kernel: str, field: str, workload: str = "random_scaling_2p26"):
-    """A per-dispatch figure of `kernel` from the committed counter summary, or
-    None when the summary is missing or the kernels changed since."""
+def _counters(workload: str = "random_scaling_2p26"):
+    """The committed rocprofv3 counter summary of `workload`, or None when it
+    is missing or the counted kernels changed since it was taken."""
     p = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
     try:
         with open(p) as f:
             c = json.load(f)
     except (OSError, ValueError):
         return None
-    if c.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    k = c.get("kernels", {}).get(kernel + "_kernel") or c.get("kernels", {}).get(kernel)
-    return None if k is None or field not in k else float(k[field])
+    return c if c.get("kernel_source_sha256") == kernel_source_hash() else None
+
+
+def measured_counter(kernel: str, field: str, workload: str = "random_scaling_2p26"):
+    """A per-dispatch figure of `kernel` from the committed counter summary
+    (None when missing or stale)."""
+    c = _counters(workload)
+    k = None if c is None else c.get("kernels", {}).get(kernel + "_kernel")
+    return None if k is None or k.get(field) is None else float(k[field])
 
 
 def counter_scale(field: str, workload: str = "random_scaling_2p26"):
     """The calibration factor `field` of the committed counter summary."""
-    try:
-        with open(os.path.join(ROOT, "profiles", f"counters_{workload}.json")) as f:
-            c = json.load(f)
-    except (OSError, ValueError):
-        return None
-    return c.get(field)
+    c = _counters(workload)
+    return None if c is None else c.get(field)
 
 
 def line_probe_rate(b, torch, dev, stream, words: int, nacc: int = 1 << 26) -> float:
@@ -670,16 +665,8 @@ def measured_traffic(kernel: str, workload: str = "random_scaling_2p26"):
     """HBM bytes per dispatch of `kernel` from the committed rocprofv3 counter
     summary (FETCH_SIZE and WRITE_SIZE, scaled by a plain copy of known size),
     or None when the summary is missing or the kernels changed since."""
-    p = os.path.join(ROOT, "profiles", f"counters_{workload}.json")
-    try:
-        with open(p) as f:
-            c = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if c.get("kernel_source_sha256") != kernel_source_hash():
-        return None
-    k = c.get("kernels", {}).get(kernel + "_kernel") or c.get("kernels", {}).get(kernel)
-    return None if k is None else int(k["bytes_scaled"])
+    v = measured_counter(kernel, "hbm_bytes", workload)
+    return None if v is None else int(v)
 
 
 def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):

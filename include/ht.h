@@ -82,11 +82,12 @@ enum {
    * is first written (compare-and-swap) into a candidate slot that the probe
    * saw empty, and the eviction chain starts only when none is left. */
   HT_FLAG_CUCKOO_PAPER_ORDER = 1u << 0,
-  /* Bucketed: read each lane's two slots with one ordinary 16-byte load
-   * instead of two 8-byte agent-scope atomic loads.  Results are identical
-   * (a stale empty slot is corrected by the compare-and-swap result); only
-   * the instruction mix differs (on gfx950 both are plain global loads). */
-  HT_FLAG_CACHED_LOADS = 1u << 1,
+  /* Bucketed, lane groups: read each lane's two slots with two 8-byte
+   * agent-scope atomic loads instead of one 16-byte load.  Results are
+   * identical (a stale empty slot is corrected by the compare-and-swap
+   * result); the 16-byte load touches a bucket with one cache request per
+   * lane group instead of two, and is the default. */
+  HT_FLAG_BUCKETED_ATOMIC_LOADS = 1u << 1,
   /* Test mode: h_j(key) is taken from a table installed with
    * ht_set_scripted_hash instead of the hash family. */
   HT_FLAG_SCRIPTED_HASH = 1u << 2,
@@ -538,19 +539,21 @@ int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access,
                  uint64_t seed, hipStream_t stream);
 
 /* Infrastructure (measurement).  The memory pattern of a find-or-put
- * kernel, without the table logic: for
- * each of n_items keys (device), read the key, make `lines_per_item` random
- * 8-byte reads (on average; each costs a whole line at the memory) in
- * d_array (n_words 64-bit words, device), then with probability
- * `cas_per_item` one random 64-bit compare-and-swap (empty -> key) there,
- * and write a 1-byte flag to d_out.  Fractions are met per item by a keyed
- * draw, in steps of 1/256.  Its time against a table kernel's on the same
- * keys, with the kernel's own read and compare-and-swap counts, tells how
- * close the kernel is to what the memory system allows for that mix.
- * HT_EINVAL for NULL pointers, an empty array, lines outside 0..64 or a
- * probability outside 0..1. */
+ * kernel, without the table logic: for each of n_items keys (device), read
+ * the key, make `lines_per_item` random 8-byte reads (on average; each costs
+ * a whole line at the memory) in d_array (n_words 64-bit words, device), then
+ * with probability `cas_per_item` one 64-bit compare-and-swap (empty -> key)
+ * there -- at a random word of its own line, or with same_line != 0 at a word
+ * of the line the first read touched, as a table kernel compare-and-swaps
+ * into the bucket or slot it has just read -- and write a 1-byte flag to
+ * d_out.  Fractions are met per item by a keyed draw, in steps of 1/256.  Its
+ * time against a table kernel's on the same keys, with the kernel's own read
+ * and compare-and-swap counts, tells how close the kernel is to what the
+ * memory system allows for that mix.  HT_EINVAL for NULL pointers, an empty
+ * array, lines outside 0..64 or a probability outside 0..1. */
 int ht_probe_mix(const uint64_t* d_keys, uint8_t* d_out, uint64_t n_items, uint64_t* d_array, uint64_t n_words,
-                 double lines_per_item, double cas_per_item, uint64_t seed, hipStream_t stream);
+                 double lines_per_item, double cas_per_item, uint32_t same_line, uint64_t seed,
+                 hipStream_t stream);
 
 #ifdef __cplusplus
 }

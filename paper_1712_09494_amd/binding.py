@@ -32,7 +32,7 @@ HT_EFULL = -3
 HT_EHIP = -4
 
 HT_FLAG_CUCKOO_PAPER_ORDER = 1 << 0
-HT_FLAG_CACHED_LOADS = 1 << 1
+HT_FLAG_BUCKETED_ATOMIC_LOADS = 1 << 1
 HT_FLAG_SCRIPTED_HASH = 1 << 2
 HT_FLAG_BUCKETED_PAPER_FULL = 1 << 3
 HT_FLAG_CUCKOO_SINGLE_PASS = 1 << 4
@@ -224,7 +224,7 @@ _PROTOS = {
     "ht_probe_copy": (C.c_int, [_vp, _vp, _u64, _vp]),
     "ht_probe_gather": (C.c_int, [_vp, _u64, _u64, _u32, _u64, _vp, _vp]),
     "ht_probe_cas": (C.c_int, [_vp, _u64, _u64, _u64, _vp]),
-    "ht_probe_mix": (C.c_int, [_vp, _vp, _u64, _vp, _u64, C.c_double, C.c_double, _u64, _vp]),
+    "ht_probe_mix": (C.c_int, [_vp, _vp, _u64, _vp, _u64, C.c_double, C.c_double, _u32, _u64, _vp]),
 }
 
 EXPORTED = tuple(_PROTOS)
@@ -579,10 +579,11 @@ def ht_probe_cas(arr, n_access: int, seed: int, stream=None) -> None:
            "ht_probe_cas")
 
 
-def ht_probe_mix(keys, out, arr, lines_per_item: float, cas_per_item: float, seed: int, stream=None) -> None:
+def ht_probe_mix(keys, out, arr, lines_per_item: float, cas_per_item: float, seed: int, stream=None,
+                 same_line: bool = False) -> None:
     _check(load().ht_probe_mix(keys.data_ptr(), out.data_ptr(), keys.numel(), arr.data_ptr(), arr.numel(),
-                               float(lines_per_item), float(cas_per_item), seed & EMPTY, _stream_handle(stream)),
-           "ht_probe_mix")
+                               float(lines_per_item), float(cas_per_item), 1 if same_line else 0, seed & EMPTY,
+                               _stream_handle(stream)), "ht_probe_mix")
 
 
 # ---- object wrapper --------------------------------------------------------------

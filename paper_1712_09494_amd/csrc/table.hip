@@ -46,8 +46,8 @@ hipError_t probe_copy(const uint64_t*, uint64_t*, uint64_t, uint32_t, hipStream_
 hipError_t probe_gather(const uint64_t*, uint64_t, uint64_t, uint32_t, uint64_t, uint64_t*, uint32_t,
                         hipStream_t);
 hipError_t probe_cas(uint64_t*, uint64_t, uint64_t, uint64_t, uint32_t, hipStream_t);
-hipError_t probe_mix(const uint64_t*, uint8_t*, uint64_t, uint64_t*, uint64_t, uint32_t, uint32_t, uint64_t, uint32_t,
-                     hipStream_t);
+hipError_t probe_mix(const uint64_t*, uint8_t*, uint64_t, uint64_t*, uint64_t, uint32_t, uint32_t, bool, uint64_t,
+                     uint32_t, hipStream_t);
 }  // namespace ht
 
 using namespace ht;
@@ -286,7 +286,7 @@ int validate_config(const ht_config* c) {
   if (c->stash_slots > 65536) return fail(HT_EINVAL, "stash_slots above 65536");
   if (c->keys_per_group != 0 && c->keys_per_group != 1 && c->keys_per_group != 2 && c->keys_per_group != 4)
     return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
-  if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_CACHED_LOADS | HT_FLAG_SCRIPTED_HASH |
+  if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_BUCKETED_ATOMIC_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS |
                              HT_FLAG_BUCKETED_ONE_LANE | HT_FLAG_CHAIN_STATS | HT_FLAG_CUCKOO_LOOKAHEAD))
     return fail(HT_EINVAL, "unknown flag bits");
@@ -459,7 +459,7 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_fop", s);
     HT_HIP(bucketed_find_or_put(d, keys, n, out, (uint32_t)blocks, R,
-                                (t->cfg.flags & HT_FLAG_CACHED_LOADS) == 0, scripted, s));
+                                (t->cfg.flags & HT_FLAG_BUCKETED_ATOMIC_LOADS) != 0, scripted, s));
     return HT_OK;
   }
   if (t->cfg.flags & HT_FLAG_CUCKOO_SINGLE_PASS) {
@@ -1118,7 +1118,7 @@ int ht_probe_cas(uint64_t* d_array, uint64_t n_words, uint64_t n_access, uint64_
 }
 
 int ht_probe_mix(const uint64_t* d_keys, uint8_t* d_out, uint64_t n_items, uint64_t* d_array, uint64_t n_words,
-                 double lines_per_item, double cas_per_item, uint64_t seed, hipStream_t s) {
+                 double lines_per_item, double cas_per_item, uint32_t same_line, uint64_t seed, hipStream_t s) {
   if (n_items == 0) return HT_OK;
   if (!d_keys || !d_out || !d_array || n_words == 0) return fail(HT_EINVAL, "NULL pointer or empty array");
   if (!(lines_per_item >= 0.0 && lines_per_item <= 64.0)) return fail(HT_EINVAL, "lines_per_item outside 0..64");
@@ -1128,7 +1128,7 @@ int ht_probe_mix(const uint64_t* d_keys, uint8_t* d_out, uint64_t n_items, uint6
   int dev = 0;
   (void)hipGetDevice(&dev);
   KernelTimer kt("probe_mix", s);
-  HT_HIP(probe_mix(d_keys, d_out, n_items, d_array, n_words, lq, cq, seed, device_cus(dev) * 8, s));
+  HT_HIP(probe_mix(d_keys, d_out, n_items, d_array, n_words, lq, cq, same_line != 0, seed, device_cus(dev) * 8, s));
   return HT_OK;
 }
 

@@ -114,9 +114,12 @@ __global__ __launch_bounds__(kBlock) void probe_cas_kernel(uint64_t* __restrict_
 // logic.  One lane per item: read the item's 8-byte key (coalesced), make
 // `lines` random 8-byte reads (whole lines at the memory) at addresses mixed
 // from the key, then with probability `cas` one random 64-bit
-// compare-and-swap (empty -> key) whose address depends on the words read,
-// and write a 1-byte flag (coalesced).  Fractional counts are met per item by
-// a keyed draw: lines_q / 256 reads on average, cas_q / 256 CAS.
+// compare-and-swap (empty -> key) whose address depends on the words read --
+// in a line of its own, or (SAME_LINE) in the line of the first read, as a
+// table kernel compare-and-swaps into the bucket or slot it has just read --
+// and write a 1-byte flag (coalesced).  Fractional counts are met per item
+// by a keyed draw: lines_q / 256 reads on average, cas_q / 256 CAS.
+template <bool SAME_LINE>
 __global__ __launch_bounds__(kBlock) void probe_mix_kernel(const uint64_t* __restrict__ keys,
                                                            uint8_t* __restrict__ out, uint64_t nitems,
                                                            uint64_t* __restrict__ a, uint64_t nwords,
@@ -126,23 +129,38 @@ __global__ __launch_bounds__(kBlock) void probe_mix_kernel(const uint64_t* __res
     const uint64_t k = keys[i];
     const uint64_t r = mix64(k ^ seed ^ 0x243f6a8885a308d3ull);
     const uint32_t nl = (lines_q >> 8) + (((uint32_t)r & 255u) < (lines_q & 255u) ? 1u : 0u);
-    uint64_t acc = 0;
-    for (uint32_t l = 0; l < nl; ++l) acc ^= a[mulhi64(mix64(k ^ seed ^ (0x9e3779b97f4a7c15ull * (l + 1))), nwords)];
+    uint64_t acc = 0, first = 0;
+    for (uint32_t l = 0; l < nl; ++l) {
+      const uint64_t w = mulhi64(mix64(k ^ seed ^ (0x9e3779b97f4a7c15ull * (l + 1))), nwords);
+      if (l == 0) first = w;
+      acc ^= a[w];
+    }
     uint8_t f = (uint8_t)(acc & 1);
     if (((uint32_t)(r >> 8) & 255u) < cas_q) {
-      const uint64_t h = mix64(k ^ seed ^ (acc & 0x100));   // issued after the reads complete
-      f = cas64(&a[mulhi64(h, nwords)], kEmpty, k) == kEmpty ? 1 : 0;
+      uint64_t w;
+      if (SAME_LINE && nl > 0) {
+        // a word of the first line read, chosen after the read completes
+        w = (first & ~15ull) + ((mix64(k ^ (acc & 0x100)) >> 60) & 15ull);
+        if (w >= nwords) w = first;
+      } else {
+        w = mulhi64(mix64(k ^ seed ^ (acc & 0x100)), nwords);   // issued after the reads complete
+      }
+      f = cas64(&a[w], kEmpty, k) == kEmpty ? 1 : 0;
     }
     out[i] = f;
   }
 }
 
 hipError_t probe_mix(const uint64_t* keys, uint8_t* out, uint64_t nitems, uint64_t* a, uint64_t nwords,
-                     uint32_t lines_q, uint32_t cas_q, uint64_t seed, uint32_t grid, hipStream_t s) {
+                     uint32_t lines_q, uint32_t cas_q, bool same_line, uint64_t seed, uint32_t grid, hipStream_t s) {
   const uint64_t need = (nitems + kBlock - 1) / kBlock;
   const uint32_t g = (uint32_t)(need < grid ? need : grid);
-  hipLaunchKernelGGL(probe_mix_kernel, dim3(g), dim3(kBlock), 0, s, keys, out, nitems, a, nwords, lines_q, cas_q,
-                     seed);
+  if (same_line)
+    hipLaunchKernelGGL(probe_mix_kernel<true>, dim3(g), dim3(kBlock), 0, s, keys, out, nitems, a, nwords, lines_q,
+                       cas_q, seed);
+  else
+    hipLaunchKernelGGL(probe_mix_kernel<false>, dim3(g), dim3(kBlock), 0, s, keys, out, nitems, a, nwords, lines_q,
+                       cas_q, seed);
   return hipGetLastError();
 }
 

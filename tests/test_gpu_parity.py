@@ -20,7 +20,7 @@ DESIGNS = {
     "bkt8": dict(kind="bucketed", bucket_slots=8),
     "bkt32": dict(kind="bucketed", bucket_slots=32),
     "bkt64": dict(kind="bucketed", bucket_slots=64),
-    "bkt16_cached": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_CACHED_LOADS),
+    "bkt16_atomic": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_BUCKETED_ATOMIC_LOADS),
     "cuckoo": dict(kind="cuckoo"),
     "cuckoo_paper": dict(kind="cuckoo", flags=b.HT_FLAG_CUCKOO_PAPER_ORDER),
     "bkt16_r1": dict(kind="bucketed", bucket_slots=16, keys_per_group=1),
@@ -35,7 +35,7 @@ DESIGNS = {
     "cuckoo_lds64k": dict(kind="cuckoo", lds_bytes=65536),
     "cuckoo_look": dict(kind="cuckoo", flags=b.HT_FLAG_CUCKOO_LOOKAHEAD),
 }
-MAIN = ["bkt16", "bkt8", "bkt16_cached", "cuckoo", "cuckoo_paper", "cuckoo_look"]
+MAIN = ["bkt16", "bkt8", "bkt16_atomic", "cuckoo", "cuckoo_paper", "cuckoo_look"]
 MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4", "bkt8_lane"]
 
 

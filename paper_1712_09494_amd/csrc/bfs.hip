@@ -15,7 +15,8 @@
 // two passes (count per state, exclusive scan of the counts, write at the
 // scanned offsets), so each state's successors sit contiguously in frontier
 // order; the batch is find-or-put as one call and the keys flagged new are
-// selected.  Scan and flagged selection use hipCUB.
+// selected in batch order.  Scan and selection are the three-pass kernels of
+// compact.hip.
 //
 // Fused levels (bucketed tables; successor generation and hash table access
 // in one kernel, as GPUexplore does, Sec. 3.2 and 7): a lane takes a frontier
@@ -26,8 +27,6 @@
 // at the scanned offsets.  The successor batch is never stored: a level moves
 // the frontier, the masks and the new states instead of writing the batch,
 // reading it for the find-or-put and again for the selection.
-#include <hipcub/hipcub.hpp>
-
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -35,6 +34,13 @@
 #include "bucketed_dev.h"
 #include "cuckoo_dev.h"
 #include "runtime.h"
+
+namespace ht {
+hipError_t scan_exclusive(const unsigned long long*, unsigned long long*, uint64_t, unsigned long long*,
+                          unsigned long long*, uint32_t, hipStream_t);
+hipError_t select_flagged(const uint64_t*, const uint8_t*, uint64_t, uint64_t*, unsigned long long*,
+                          unsigned long long*, uint32_t, hipStream_t);
+}  // namespace ht
 
 using namespace ht;
 using namespace ht_rt;
@@ -414,7 +420,9 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
   const uint32_t grid = max_blocks(t);
   rc = frontier.ensure(8);
   if (!rc) rc = nsel.ensure(16);
+  if (!rc) rc = tmp.ensure((grid + 1) * 8ull);   // block totals of the scans and the selection
   if (rc) return rc;
+  auto* wk = static_cast<unsigned long long*>(tmp.p);
   HT_HIP(hipMemcpyAsync(frontier.p, &initial, 8, hipMemcpyHostToDevice, s));
   rc = do_find_or_put(t, static_cast<uint64_t*>(frontier.p), 1, nullptr, s);
   if (rc) return rc;
@@ -439,10 +447,6 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
     auto* ns = static_cast<unsigned long long*>(nsel.p);
     auto* mk = static_cast<uint64_t*>(masks.p);
     const uint32_t g1 = (uint32_t)std::min<uint64_t>((nf + kBlock - 1) / kBlock, grid);
-    size_t tb = 0;
-    HT_HIP(hipcub::DeviceScan::ExclusiveSum(nullptr, tb, cnt, off, (int)nf, s));
-    rc = tmp.ensure(std::max<size_t>(tb, 256));
-    if (rc) break;
     if (fused && !ck) HT_HIP(hipMemsetAsync(ns, 0, 8, s));
     double lms = 0.0;
     // span 1: successor counts (split, fused Cuckoo) or the fused bucketed pass, then a scan
@@ -456,7 +460,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       hipLaunchKernelGGL(bfs_count_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, cnt);
       HT_HIP(hipGetLastError());
     }
-    HT_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, cnt, off, (int)nf, s));
+    HT_HIP(scan_exclusive(cnt, off, nf, ns + 1, wk, grid, s));
     HT_HIP(hipEventRecord(ev[1], s));
     unsigned long long last[3] = {0, 0, 0};
     HT_HIP(hipMemcpyAsync(&last[0], off + nf - 1, 8, hipMemcpyDeviceToHost, s));
@@ -488,7 +492,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       hipLaunchKernelGGL(bfs_cuckoo_scrub_kernel, dim3(g2), dim3(kBlock), 0, s, nf, off, sc, gc);
       HT_HIP(hipGetLastError());
       HT_HIP(hipEventRecord(ev[7], s));
-      HT_HIP(hipcub::DeviceScan::ExclusiveSum(tmp.p, tb, cnt, noff, (int)nf, s));
+      HT_HIP(scan_exclusive(cnt, noff, nf, ns + 1, wk, grid, s));
       HT_HIP(hipEventRecord(ev[3], s));
       unsigned long long lastn[2] = {0, 0};
       HT_HIP(hipMemcpyAsync(&lastn[0], noff + nf - 1, 8, hipMemcpyDeviceToHost, s));
@@ -498,10 +502,6 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       nnew = lastn[0] + lastn[1];
     }
     if (fused) {
-      if (nnew >= (1ull << 31)) {   // the next level's scans count in int
-        rc = fail(HT_EINVAL, "a level's new states exceed 2^31");
-        break;
-      }
       // last span: the new states written at their scanned offsets
       rc = next.ensure(std::max<uint64_t>(nnew, 1) * 8);
       if (rc) break;
@@ -515,10 +515,6 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       lms += span_ms(ev[4], ev[5]);
       if (fop_ms) fop_ms[L] = span_ms(ev[6], ev[7]);
     } else {
-      if (nb >= (1ull << 31)) {
-        rc = fail(HT_EINVAL, "a level's batch exceeds 2^31 keys");
-        break;
-      }
       rc = batch.ensure(std::max<uint64_t>(nb, 1) * 8);
       if (!rc) rc = flags.ensure(std::max<uint64_t>(nb, 1));
       if (!rc) rc = next.ensure(std::max<uint64_t>(nb, 1) * 8);
@@ -526,10 +522,6 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       if (rc) break;
       auto* bt = static_cast<uint64_t*>(batch.p);
       auto* fl = static_cast<uint8_t*>(flags.p);
-      size_t tbs = 0;
-      HT_HIP(hipcub::DeviceSelect::Flagged(nullptr, tbs, bt, fl, static_cast<uint64_t*>(next.p), ns, (int)nb, s));
-      rc = tmp.ensure(std::max<size_t>(tbs, 256));
-      if (rc) break;
       // span 2: write the batch, find-or-put it, select the new keys
       HT_HIP(hipEventRecord(ev[2], s));
       hipLaunchKernelGGL(bfs_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, off, bt);
@@ -538,7 +530,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       rc = do_find_or_put(t, bt, nb, fl, s);
       if (rc) break;
       HT_HIP(hipEventRecord(ev[7], s));
-      HT_HIP(hipcub::DeviceSelect::Flagged(tmp.p, tbs, bt, fl, static_cast<uint64_t*>(next.p), ns, (int)nb, s));
+      HT_HIP(select_flagged(bt, fl, nb, static_cast<uint64_t*>(next.p), ns, wk, grid, s));
       HT_HIP(hipEventRecord(ev[3], s));
       unsigned long long nsv = 0;
       HT_HIP(hipMemcpyAsync(&nsv, ns, 8, hipMemcpyDeviceToHost, s));

@@ -46,7 +46,7 @@ def source_hash() -> str:
 def short_name(full: str) -> str:
     """Function name without namespace, return type and arguments; template
     arguments kept for the probe kernels only."""
-    s = full.strip()
+    s = full.strip().replace("(anonymous namespace)::", "")
     if s.startswith("void "):
         s = s[5:]
     s = s.split("(")[0].replace("ht::", "").replace("at::native::", "")

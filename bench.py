@@ -4,9 +4,10 @@ Workload (random-key scaling case): 2^26 uniform-random 64-bit keys with 10%
 duplicates (60,397,978 distinct), inserted by find-or-put in consecutive
 batches of 2^20 into a table sized for load factor 0.7.  One step = clear the
 table and find-or-put the whole sequence, for the bucketed table (B = 8
-slots = 64-byte buckets, c = 3; the autotuner's pick for this shape) and for
-the Cuckoo table (c = 3), i.e. 2 x 2^26 find-or-put operations.  Keys are
-resident in HBM before the timed region starts.
+slots = 64-byte buckets, c = 3) and for the Cuckoo table (c = 4), the
+fastest bucket width and hash counts measured for this shape, i.e.
+2 x 2^26 find-or-put operations.  Keys are resident in HBM before the timed
+region starts.
 
 The last stdout line is one compact JSON object (a few KB): the headline
 value (whole-step find-or-put Mops/s), the roofline of the dominant kernel
@@ -54,6 +55,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--designs", default="bucketed,cuckoo")
     ap.add_argument("--bucket-slots", type=int, default=8)
+    ap.add_argument("--cuckoo-nhash", type=int, default=4)
     ap.add_argument("--copy-calib", action="store_true",
                     help="after the timed steps, copy 2^26 words once (counter calibration)")
     ap.add_argument("--no-batched", action="store_true")
@@ -138,7 +140,7 @@ def main():
             tables[name] = b.Table("bucketed", capacity=cap, nhash=3, bucket_slots=args.bucket_slots,
                                    max_batch=args.batch)
         else:
-            tables[name] = b.Table("cuckoo", capacity=cap, nhash=3, max_batch=args.batch)
+            tables[name] = b.Table("cuckoo", capacity=cap, nhash=args.cuckoo_nhash, max_batch=args.batch)
 
     def fop_all(t):
         for s0 in range(0, args.n, args.batch):
@@ -169,7 +171,7 @@ def main():
     res["warmup"] = args.warmup
     res["config"] = {"workload": "random-key scaling: 2^26 uniform 64-bit keys, 10% duplicates, "
                                  f"find-or-put in batches of {args.batch} at load factor {args.lf}; "
-                                 f"bucketed (B={args.bucket_slots}, c=3) + cuckoo (c=3) per step",
+                                 f"bucketed (B={args.bucket_slots}, c=3) + cuckoo (c={args.cuckoo_nhash}) per step",
                      "keys": args.n, "distinct": d, "batch": args.batch, "load_factor": args.lf,
                      "designs": designs}
 
@@ -235,7 +237,8 @@ def main():
                                ("bucketed_b16", "bucketed", dict(bucket_slots=16)),
                                ("bucketed_b16_paper_full", "bucketed",
                                 dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL))):
-            t = b.Table(kind, capacity=cap, nhash=3, max_batch=args.batch, **kw)
+            t = b.Table(kind, capacity=cap, nhash=args.cuckoo_nhash if kind == "cuckoo" else 3,
+                        max_batch=args.batch, **kw)
             per_batch_times(t)                                # warm-up fill
             row = design_row(per_batch_times(t))
             st = t.stats()
@@ -263,7 +266,7 @@ def main():
     # time -- is the headline), each beside the mixed probe of its own memory
     # pattern and the chip's random-CAS and random-line rates
     full_size = args.batch == 1 << 20 and args.n == 1 << 26
-    rls = kernel_rooflines(per_kernel, args, d, cap, new_per_batch)
+    rls = kernel_rooflines(per_kernel, args, d, cap, new_per_batch, args.cuckoo_nhash)
     if rls and not args.no_mix:
         for name, rl in rls.items():
             rl["mix"] = mix_probe(b, torch, dev, stream, keys[:rl["keys_per_launch"]], cap,
@@ -294,9 +297,9 @@ def main():
     if "cuckoo" in tables and not args.no_evict_profile:
         # the evict kernel's launches and chains, with the plain chain of Sec. 4.1
         # and with the lookahead before each exchange
-        res["cuckoo_evict"] = evict_profile(b, torch, cap, keys, out, args.n, args.batch)
+        res["cuckoo_evict"] = evict_profile(b, torch, cap, keys, out, args.n, args.batch, args.cuckoo_nhash)
         res["cuckoo_evict_lookahead"] = evict_profile(b, torch, cap, keys, out, args.n, args.batch,
-                                                      flags=b.HT_FLAG_CUCKOO_LOOKAHEAD)
+                                                      args.cuckoo_nhash, flags=b.HT_FLAG_CUCKOO_LOOKAHEAD)
         for k in ("cuckoo_evict", "cuckoo_evict_lookahead"):
             r = res[k]
             log(f"[bench] {k}: avg {r['avg_ms']} ms, max {r['max_ms']} ms, fill kernels {r['fill_kernels_ms']} ms, "
@@ -513,7 +516,7 @@ def kernel_bytes(name, n, d_new, c, bucket_slots, alpha=0.0):
     return None if m is None else m["bytes"]
 
 
-def fill_model(name, args, d, cap, new_per_batch):
+def fill_model(name, args, d, cap, new_per_batch, c=3):
     """The per-launch model averaged over the launches of the W2 fill: batch
     b holds n_b keys, new_b of them new, and runs at the load halfway through
     it."""
@@ -525,7 +528,7 @@ def fill_model(name, args, d, cap, new_per_batch):
     for i, new in enumerate(new_per_batch):
         n_b = min(args.batch, args.n - i * args.batch)
         alpha = (done + new / 2) / cap
-        m = kernel_model(name, n_b, new, 3, args.bucket_slots, alpha)
+        m = kernel_model(name, n_b, new, c if name == "cuckoo_probe" else 3, args.bucket_slots, alpha)
         if m is None:
             return None
         for k in acc:
@@ -534,7 +537,7 @@ def fill_model(name, args, d, cap, new_per_batch):
     return acc
 
 
-def kernel_rooflines(per_kernel, args, d, cap, new_per_batch):
+def kernel_rooflines(per_kernel, args, d, cap, new_per_batch, cuckoo_c=3):
     """Roofline entry of each find-or-put kernel of the W2 fill: modeled bytes
     per launch over the HIP-event average launch time, against 8 TB/s, with
     the counter-measured traffic (committed rocprofv3 summary, when current)."""
@@ -543,7 +546,7 @@ def kernel_rooflines(per_kernel, args, d, cap, new_per_batch):
     for name in ("bucketed_fop", "cuckoo_probe"):
         if name not in per_kernel:
             continue
-        m = fill_model(name, args, d, cap, new_per_batch)
+        m = fill_model(name, args, d, cap, new_per_batch, cuckoo_c)
         if m is None:
             continue
         avg_ms = per_kernel[name]["avg_ms"]
@@ -579,12 +582,14 @@ def mix_probe(b, torch, dev, stream, keys, words, lines, cas, kernel_ms, reps=5)
     return res
 
 
-def evict_profile(b, torch, cap, keys, out, n, batch, flags=0):
+def evict_profile(b, torch, cap, keys, out, n, batch, c, flags=0):
     """Per-launch durations of the Cuckoo evict kernel over one W2 fill of a
-    table of `cap` slots (c = 3) created with the chain-length histogram on
-    (the library's per-kernel events, read after every batch; a warm-up fill
-    first), the exchanges of the fill and the histogram of its chains."""
-    t = b.Table("cuckoo", capacity=cap, nhash=3, max_batch=batch, flags=flags | b.HT_FLAG_CHAIN_STATS)
+    table of `cap` slots and c hash functions (the library's per-kernel
+    events, read after every batch; a warm-up fill first), the exchanges of
+    the fill, and the histogram of its chains from a second fill of a table
+    with the chain-length histogram on (its atomics slow the kernel, so that
+    fill is not timed)."""
+    t = b.Table("cuckoo", capacity=cap, nhash=c, max_batch=batch, flags=flags)
     for s0 in range(0, n, batch):
         t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
     t.clear()
@@ -601,8 +606,12 @@ def evict_profile(b, torch, cap, keys, out, n, batch, flags=0):
         prev = total
     b.ht_timing_enable(False)
     st = t.stats()
-    hist = b.ht_chain_histogram(t.handle)
     t.close()
+    th = b.Table("cuckoo", capacity=cap, nhash=c, max_batch=batch, flags=flags | b.HT_FLAG_CHAIN_STATS)
+    for s0 in range(0, n, batch):
+        th.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
+    hist = b.ht_chain_histogram(th.handle)
+    th.close()
     per = np.array(per)
     return {"avg_ms": round(float(per.mean()), 5), "max_ms": round(float(per.max()), 5),
             "p99_ms": round(float(np.percentile(per, 99)), 5), "launches": int(per.size),

@@ -487,11 +487,13 @@ def cuckoo_lines(alpha: float, c: int) -> float:
     return sum(alpha ** j for j in range(c))
 
 
-def kernel_model(name, n, d_new, c, bucket_slots, alpha=0.0):
+def kernel_model(name, n, d_new, c, bucket_slots, alpha=0.0, scrubbed=0.0):
     """Bytes a kernel must move for a batch of n keys of which d_new are new,
     at table load alpha (the fraction of slots in use while it runs), with the
     random lines and compare-and-swaps per key behind it; None for kernels
-    without a model."""
+    without a model.  `scrubbed`: deduplication-set slots the previous call's
+    winners took, which the Cuckoo probe kernel empties (an 8-byte record
+    entry read and an 8-byte word written each)."""
     if name == "bucketed_fop":
         # key + flag + the first bucket's line(s); each new key's compare-and-swap
         # dirties one half-line
@@ -506,8 +508,8 @@ def kernel_model(name, n, d_new, c, bucket_slots, alpha=0.0):
         lines = cuckoo_lines(alpha, c)
         listed = d_new * alpha ** c
         placed = d_new - listed
-        return {"bytes": n * (9 + LINE * lines) + placed * HALF + 16 * listed, "lines_per_key": lines,
-                "cas_per_key": placed / n}
+        return {"bytes": n * (9 + LINE * lines) + placed * HALF + 16 * listed + 16 * scrubbed,
+                "lines_per_key": lines, "cas_per_key": placed / n, "listed": listed}
     return None
 
 
@@ -523,16 +525,22 @@ def fill_model(name, args, d, cap, new_per_batch, c=3):
     nb = (args.n + args.batch - 1) // args.batch
     if not new_per_batch:
         new_per_batch = [d / nb] * nb
+    cc = c if name == "cuckoo_probe" else 3
+    # the Cuckoo probe kernel empties the set slots of the previous call's
+    # listed keys; the fill repeats, so the first call follows the last one
+    last_alpha = (d - new_per_batch[-1] / 2) / cap
+    prev_listed = new_per_batch[-1] * last_alpha ** cc if name == "cuckoo_probe" else 0.0
     done = 0.0
     acc = {"bytes": 0.0, "lines_per_key": 0.0, "cas_per_key": 0.0}
     for i, new in enumerate(new_per_batch):
         n_b = min(args.batch, args.n - i * args.batch)
         alpha = (done + new / 2) / cap
-        m = kernel_model(name, n_b, new, c if name == "cuckoo_probe" else 3, args.bucket_slots, alpha)
+        m = kernel_model(name, n_b, new, cc, args.bucket_slots, alpha, prev_listed)
         if m is None:
             return None
         for k in acc:
             acc[k] += m[k] / nb
+        prev_listed = m.get("listed", 0.0)
         done += new
     return acc
 

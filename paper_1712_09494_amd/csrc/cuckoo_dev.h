@@ -264,11 +264,29 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
   return nnew;
 }
 
+// Empty the set slots the previous call's winners took (deferred scrub).  It
+// runs in the probe kernel, which never touches the set, and the kernel
+// boundary orders it before this call's evict kernel; the previous call's
+// regions are spread over this call's waves.
+__device__ __forceinline__ void cuckoo_scrub_deferred(const CuckooScratch& s, uint64_t wave, uint64_t nwaves) {
+  const int lane = lane_id();
+  const uint64_t regions = s.dirty_desc[0];
+  const uint64_t pw = s.dirty_desc[1];
+  for (uint64_t r = wave; r < regions; r += nwaves) {
+    const uint32_t cnt = s.dirty_cnt[r];
+    for (uint32_t e = lane; e < cnt; e += kWave) {
+      const uint64_t p = s.dirty[r * pw + e];
+      if (p != ~0ull) s.dset[p] = kEmpty;
+    }
+  }
+}
+
 template <int R, bool SCRIPTED, bool PAPER_ORDER>
 __global__ __launch_bounds__(kBlock) void cuckoo_probe_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                                uint64_t n, uint8_t* __restrict__ out,
                                                                CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
+  if (s.dirty) cuckoo_scrub_deferred(s, wave, (uint64_t)gridDim.x * (kBlock / kWave));
   wave_count(t.ctr->size, cuckoo_probe_region<R, SCRIPTED, PAPER_ORDER>(t, keys, n, out, s, wave), (uint32_t)wave);
 }
 
@@ -351,8 +369,9 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
       p = (p + 1) & s.dset_mask;
     }
     if (out) out[meta & kIdxMask] = winner ? 1 : 0;
-    // remember the scratch-set slot for the scrub kernel (~0: nothing to clear)
-    s.wmeta[begin + e] = winner ? p : ~0ull;
+    // remember the scratch-set slot for the scrub (~0: nothing to clear)
+    if (s.dirty) s.dirty[begin + e] = winner ? p : ~0ull;
+    else s.wmeta[begin + e] = winner ? p : ~0ull;
     if (!winner) continue;
     uint64_t y = k;
     uint32_t steps = 0;
@@ -361,6 +380,7 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
     chain_record(t, steps, placed, wave);
     ++nnew;
   }
+  if (s.dirty && lane == 0) s.dirty_cnt[wave] = cnt;
 }
 
 template <bool SCRIPTED>
@@ -368,6 +388,10 @@ __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64
                                                                CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   unsigned long long nnew = 0, nevict = 0;
+  if (s.dirty && wave == 0 && lane_id() == 0) {
+    s.dirty_desc[0] = (uint64_t)gridDim.x * (kBlock / kWave);
+    s.dirty_desc[1] = s.per_wave;
+  }
   cuckoo_evict_region<SCRIPTED>(t, n, out, s, wave, nnew, nevict);
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
@@ -437,9 +461,9 @@ __global__ __launch_bounds__(kBlock) void cuckoo_single_pass_kernel(DevTable t, 
   wave_count(t.ctr->evictions, nevict, (uint32_t)(first / kWave));
 }
 
-// Kernel 3: empty the scratch-set slots the winners of kernel 2 took.  It
-// runs after kernel 2 has finished, so no copy of a key can find its slot
-// empty and win a second time.
+// Kernel 3 (calls without the deferred scrub): empty the scratch-set slots
+// the winners of kernel 2 took.  It runs after kernel 2 has finished, so no
+// copy of a key can find its slot empty and win a second time.
 __device__ __forceinline__ void cuckoo_scrub_region(uint64_t n, const CuckooScratch& s, uint64_t wave) {
   const int lane = lane_id();
   const uint64_t begin = wave * s.per_wave;

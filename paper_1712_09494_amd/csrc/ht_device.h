@@ -102,13 +102,19 @@ struct DevTable {
 
 // Scratch of the Cuckoo find-or-put (owned by the table).
 struct CuckooScratch {
-  uint64_t* dset;        // deduplication set, dset_mask + 1 words, all empty between calls
+  uint64_t* dset;        // deduplication set, dset_mask + 1 words, all empty when an evict kernel starts
   uint64_t dset_mask;
   uint64_t dset_seed;
   uint64_t* wkey;        // listed keys, per-wave regions
   uint64_t* wmeta;       // key index (scratch-set slot once the evict kernel has run)
   uint32_t* wcnt;        // listed keys per wave
   uint64_t per_wave;     // keys (and list room) per wave
+  // Deferred scrub (single-table calls; NULL elsewhere): the evict kernel
+  // records the set slots its winners took here instead of in wmeta, and the
+  // next call's probe kernel empties them, so no third kernel runs.
+  uint64_t* dirty;       // set slot per listed key (~0: none), per-wave regions
+  uint32_t* dirty_cnt;   // entries per wave
+  uint64_t* dirty_desc;  // [0] = waves of the call that wrote them, [1] = its keys per wave
 };
 
 template <bool SCRIPTED>

@@ -40,6 +40,12 @@ struct ht_table {
   uint64_t* wkey = nullptr;
   uint64_t* wmeta = nullptr;
   uint32_t* wcnt = nullptr;
+  // deferred scrub of the single-table Cuckoo find-or-put: its own set and
+  // the record of the slots the last such call took (no other path uses them)
+  uint64_t* dset_defer = nullptr;
+  uint64_t* dirty = nullptr;
+  uint32_t* dirty_cnt = nullptr;
+  uint64_t* dirty_desc = nullptr;
   // scripted hashes
   ht::ScriptRow* script = nullptr;
   uint32_t nscript = 0;

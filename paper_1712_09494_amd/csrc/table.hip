@@ -233,6 +233,10 @@ int free_scratch(ht_table* t) {
   t->wkey = nullptr;
   t->wmeta = nullptr;
   t->wcnt = nullptr;
+  t->dset_defer = nullptr;
+  t->dirty = nullptr;
+  t->dirty_cnt = nullptr;
+  t->dirty_desc = nullptr;
   t->scratch_n = 0;
   t->dset_slots = 0;
   return HT_OK;
@@ -252,8 +256,12 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   const size_t b_dset = align_up(ds * 8, 256);
   const size_t b_k = align_up(n * 8, 256);
   const size_t b_c = align_up(nw * 4, 256);   // wcnt
+  // single-word Cuckoo tables: a second set, the slot record and its count
+  // per wave for the deferred scrub, and two words describing that record
+  const bool defer = t->cfg.kind == HT_CUCKOO && t->cfg.key_words <= 1;
+  const size_t b_defer = defer ? b_dset + b_k + b_c + 256 : 0;
   void* p = nullptr;
-  hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c);
+  hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c + b_defer);
   if (e != hipSuccess) {
     (void)hipGetLastError();
     return fail(HT_ENOMEM, std::string("hipMalloc of find-or-put scratch failed: ") + hipGetErrorString(e));
@@ -263,9 +271,20 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   t->wkey = reinterpret_cast<uint64_t*>(c + b_dset);
   t->wmeta = reinterpret_cast<uint64_t*>(c + b_dset + b_k);
   t->wcnt = reinterpret_cast<uint32_t*>(c + b_dset + 2 * b_k);
+  if (defer) {
+    char* d = c + b_dset + 2 * b_k + b_c;
+    t->dset_defer = reinterpret_cast<uint64_t*>(d);
+    t->dirty = reinterpret_cast<uint64_t*>(d + b_dset);
+    t->dirty_cnt = reinterpret_cast<uint32_t*>(d + b_dset + b_k);
+    t->dirty_desc = reinterpret_cast<uint64_t*>(d + b_dset + b_k + b_c);
+  }
   t->dset_slots = ds;
   t->scratch_n = n;
   HT_HIP(fill_words(t->dset, ds, kEmpty, max_blocks(t), nullptr));
+  if (defer) {
+    HT_HIP(fill_words(t->dset_defer, ds, kEmpty, max_blocks(t), nullptr));
+    HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->dirty_desc), 4, nullptr));   // no record yet
+  }
   HT_HIP(hipDeviceSynchronize());
   return HT_OK;
 }
@@ -475,6 +494,12 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     int rc = reserve_scratch(t, n);
     if (rc != HT_OK) return rc;
     sc = scratch_view(t, n);
+    // deferred scrub: this path's own set, emptied by the next call's probe
+    // kernel; the record describes the slots this call's winners take
+    sc.dset = t->dset_defer;
+    sc.dirty = t->dirty;
+    sc.dirty_cnt = t->dirty_cnt;
+    sc.dirty_desc = t->dirty_desc;
   }
   const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
   const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
@@ -489,7 +514,7 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     KernelTimer kt("cuckoo_evict", s);
     HT_HIP(cuckoo_evict(d, n, out, sc, (uint32_t)blocks, scripted, s));
   }
-  {
+  if (!sc.dirty) {
     KernelTimer kt("cuckoo_scrub", s);
     HT_HIP(cuckoo_scrub(n, sc, (uint32_t)blocks, s));
   }

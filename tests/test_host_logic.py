@@ -60,6 +60,9 @@ def test_bench_byte_model():
     assert bench.kernel_bytes("bucketed_fop", n, d, 3, 64) == n * (9 + 4 * 128) + d * 64
     assert bench.kernel_bytes("cuckoo_probe", n, d, 3, 8) == n * (9 + 128) + d * 64
     assert bench.kernel_bytes("cuckoo_evict", n, d, 3, 8) is None
+    # the probe kernel also empties the set slots of the previous call's winners
+    assert (bench.kernel_model("cuckoo_probe", n, d, 3, 8, 0.5, scrubbed=1000)["bytes"]
+            == bench.kernel_model("cuckoo_probe", n, d, 3, 8, 0.5)["bytes"] + 16 * 1000)
     h = bench.kernel_source_hash()
     assert len(h) == 64 and h == bench.kernel_source_hash()
 

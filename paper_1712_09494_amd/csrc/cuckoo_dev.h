@@ -266,16 +266,25 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
 
 // Empty the set slots the previous call's winners took (deferred scrub).  It
 // runs in the probe kernel, which never touches the set, and the kernel
-// boundary orders it before this call's evict kernel; the previous call's
-// regions are spread over this call's waves.
-__device__ __forceinline__ void cuckoo_scrub_deferred(const CuckooScratch& s, uint64_t wave, uint64_t nwaves) {
+// boundary orders it before this call's evict kernel.  Wave w takes the
+// record of the previous call's wave w (and of waves w + nwaves, ... when
+// that call had more); `regions`, `cnt0` and `p0` (this wave's count and
+// each lane's first entry) were loaded when the kernel started, so only the
+// stores remain here.
+__device__ __forceinline__ void cuckoo_scrub_deferred(const CuckooScratch& s, uint64_t wave, uint64_t nwaves,
+                                                      uint64_t regions, uint32_t cnt0, uint64_t p0) {
   const int lane = lane_id();
-  const uint64_t regions = s.dirty_desc[0];
-  const uint64_t pw = s.dirty_desc[1];
-  for (uint64_t r = wave; r < regions; r += nwaves) {
+  if (wave < regions) {
+    if ((uint32_t)lane < cnt0 && p0 != ~0ull) s.dset[p0] = kEmpty;
+    for (uint32_t e = lane + kWave; e < cnt0; e += kWave) {
+      const uint64_t p = s.dirty[wave * s.dirty_stride + e];
+      if (p != ~0ull) s.dset[p] = kEmpty;
+    }
+  }
+  for (uint64_t r = wave + nwaves; r < regions; r += nwaves) {
     const uint32_t cnt = s.dirty_cnt[r];
     for (uint32_t e = lane; e < cnt; e += kWave) {
-      const uint64_t p = s.dirty[r * pw + e];
+      const uint64_t p = s.dirty[r * s.dirty_stride + e];
       if (p != ~0ull) s.dset[p] = kEmpty;
     }
   }
@@ -286,8 +295,21 @@ __global__ __launch_bounds__(kBlock) void cuckoo_probe_kernel(DevTable t, const 
                                                                uint64_t n, uint8_t* __restrict__ out,
                                                                CuckooScratch s) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
-  if (s.dirty) cuckoo_scrub_deferred(s, wave, (uint64_t)gridDim.x * (kBlock / kWave));
+  const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
+  // the deferred scrub's loads go out with the first keys' loads
+  uint64_t regions = 0, p0 = ~0ull;
+  uint32_t cnt0 = 0;
+  if (s.dirty) {
+    // a vector load (the pointer in vector registers), so that nothing waits
+    // for it before the probe starts
+    const uint64_t* desc = s.dirty_desc;
+    asm volatile("" : "+v"(desc));
+    regions = *(const __attribute__((address_space(1))) uint64_t*)desc;
+    cnt0 = s.dirty_cnt[wave];
+    p0 = s.dirty[wave * s.dirty_stride + lane_id()];
+  }
   wave_count(t.ctr->size, cuckoo_probe_region<R, SCRIPTED, PAPER_ORDER>(t, keys, n, out, s, wave), (uint32_t)wave);
+  if (s.dirty) cuckoo_scrub_deferred(s, wave, nwaves, regions, cnt0, p0);
 }
 
 // Eviction chain of Sec. 4.1 for key x starting at slot index `slot` (which
@@ -370,7 +392,7 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
     }
     if (out) out[meta & kIdxMask] = winner ? 1 : 0;
     // remember the scratch-set slot for the scrub (~0: nothing to clear)
-    if (s.dirty) s.dirty[begin + e] = winner ? p : ~0ull;
+    if (s.dirty) s.dirty[wave * s.dirty_stride + e] = winner ? p : ~0ull;
     else s.wmeta[begin + e] = winner ? p : ~0ull;
     if (!winner) continue;
     uint64_t y = k;
@@ -390,7 +412,6 @@ __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64
   unsigned long long nnew = 0, nevict = 0;
   if (s.dirty && wave == 0 && lane_id() == 0) {
     s.dirty_desc[0] = (uint64_t)gridDim.x * (kBlock / kWave);
-    s.dirty_desc[1] = s.per_wave;
   }
   cuckoo_evict_region<SCRIPTED>(t, n, out, s, wave, nnew, nevict);
   wave_count(t.ctr->size, nnew, (uint32_t)wave);

@@ -112,9 +112,10 @@ struct CuckooScratch {
   // Deferred scrub (single-table calls; NULL elsewhere): the evict kernel
   // records the set slots its winners took here instead of in wmeta, and the
   // next call's probe kernel empties them, so no third kernel runs.
-  uint64_t* dirty;       // set slot per listed key (~0: none), per-wave regions
+  uint64_t* dirty;       // set slot per listed key (~0: none); wave w's at w * dirty_stride
   uint32_t* dirty_cnt;   // entries per wave
-  uint64_t* dirty_desc;  // [0] = waves of the call that wrote them, [1] = its keys per wave
+  uint64_t* dirty_desc;  // [0] = waves of the call that wrote them
+  uint64_t dirty_stride; // entries per wave (>= per_wave)
 };
 
 template <bool SCRIPTED>

@@ -46,6 +46,7 @@ struct ht_table {
   uint64_t* dirty = nullptr;
   uint32_t* dirty_cnt = nullptr;
   uint64_t* dirty_desc = nullptr;
+  uint64_t dirty_stride = 0;
   // scripted hashes
   ht::ScriptRow* script = nullptr;
   uint32_t nscript = 0;

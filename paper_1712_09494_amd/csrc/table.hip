@@ -237,6 +237,7 @@ int free_scratch(ht_table* t) {
   t->dirty = nullptr;
   t->dirty_cnt = nullptr;
   t->dirty_desc = nullptr;
+  t->dirty_stride = 0;
   t->scratch_n = 0;
   t->dset_slots = 0;
   return HT_OK;
@@ -256,10 +257,14 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   const size_t b_dset = align_up(ds * 8, 256);
   const size_t b_k = align_up(n * 8, 256);
   const size_t b_c = align_up(nw * 4, 256);   // wcnt
-  // single-word Cuckoo tables: a second set, the slot record and its count
-  // per wave for the deferred scrub, and two words describing that record
+  // single-word Cuckoo tables: a second set, the slot record (a fixed
+  // stride per wave, at least the keys per wave of any launch: 64 * R <= 256
+  // below the full grid, n / waves at it) and its count per wave for the
+  // deferred scrub, and a word with the record's wave count
   const bool defer = t->cfg.kind == HT_CUCKOO && t->cfg.key_words <= 1;
-  const size_t b_defer = defer ? b_dset + b_k + b_c + 256 : 0;
+  const uint64_t stride = std::max<uint64_t>(256, (n + nw - 1) / nw);
+  const size_t b_rec = align_up(nw * stride * 8, 256);
+  const size_t b_defer = defer ? b_dset + b_rec + b_c + 256 : 0;
   void* p = nullptr;
   hipError_t e = hipMalloc(&p, b_dset + 2 * b_k + b_c + b_defer);
   if (e != hipSuccess) {
@@ -275,8 +280,9 @@ int reserve_scratch(ht_table* t, uint64_t n) {
     char* d = c + b_dset + 2 * b_k + b_c;
     t->dset_defer = reinterpret_cast<uint64_t*>(d);
     t->dirty = reinterpret_cast<uint64_t*>(d + b_dset);
-    t->dirty_cnt = reinterpret_cast<uint32_t*>(d + b_dset + b_k);
-    t->dirty_desc = reinterpret_cast<uint64_t*>(d + b_dset + b_k + b_c);
+    t->dirty_cnt = reinterpret_cast<uint32_t*>(d + b_dset + b_rec);
+    t->dirty_desc = reinterpret_cast<uint64_t*>(d + b_dset + b_rec + b_c);
+    t->dirty_stride = stride;
   }
   t->dset_slots = ds;
   t->scratch_n = n;
@@ -500,11 +506,13 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     sc.dirty = t->dirty;
     sc.dirty_cnt = t->dirty_cnt;
     sc.dirty_desc = t->dirty_desc;
+    sc.dirty_stride = t->dirty_stride;
   }
   const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
   const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
   const uint64_t nwaves = blocks * 4;
   sc.per_wave = (n + nwaves - 1) / nwaves;
+  if (sc.dirty && sc.per_wave > sc.dirty_stride) return fail(HT_EINVAL, "internal: scrub record stride too small");
   const bool paper = (t->cfg.flags & HT_FLAG_CUCKOO_PAPER_ORDER) != 0;
   {
     KernelTimer kt("cuckoo_probe", s);

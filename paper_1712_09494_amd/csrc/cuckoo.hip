@@ -58,12 +58,18 @@ hipError_t cuckoo_single_pass(const DevTable& t, const uint64_t* keys, uint64_t 
 }
 
 // Kernel 2: deduplicate the listed keys and run their eviction chains.
+// `grid`: the probe kernel's blocks; the evict kernel runs one wave per
+// `pack` of its waves' regions.
 hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const CuckooScratch& s, uint32_t grid,
-                        bool scripted, hipStream_t st) {
+                        uint32_t pack, bool scripted, hipStream_t st) {
+  if (pack < 1 || pack > kMaxPack) return hipErrorInvalidValue;
+  const uint64_t nregions = (uint64_t)grid * (kBlock / kWave);
+  const uint64_t waves = (nregions + pack - 1) / pack;
+  const uint32_t g = (uint32_t)((waves + kBlock / kWave - 1) / (kBlock / kWave));
   if (scripted)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(grid), dim3(kBlock), t.lds, st, t, n, out, s);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions, pack);
   else
-    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(grid), dim3(kBlock), t.lds, st, t, n, out, s);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions, pack);
   return hipGetLastError();
 }
 

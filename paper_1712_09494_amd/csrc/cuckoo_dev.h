@@ -372,16 +372,38 @@ __device__ __forceinline__ void chain_record(const DevTable& t, uint32_t steps, 
 
 // Kernel 2: evict.  The keys kernel 1 listed are deduplicated in the
 // scratch set; each winner reports 1 and runs the eviction chain from h_1.
+// A wave serves the lists of `m` consecutive regions r0 .. r0+m-1 (m <=
+// kMaxPack) as one list, so its lanes stay busy when each region listed
+// fewer keys than a wave has lanes.
+constexpr uint32_t kMaxPack = 8;
+
 template <bool SCRIPTED>
-__device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
-                                                    const CuckooScratch& s, uint64_t wave,
-                                                    unsigned long long& nnew, unsigned long long& nevict) {
+__device__ __forceinline__ void cuckoo_evict_regions(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
+                                                     const CuckooScratch& s, uint64_t r0, uint32_t m,
+                                                     unsigned long long& nnew, unsigned long long& nevict) {
   const int lane = lane_id();
-  const uint64_t begin = wave * s.per_wave;
-  const uint32_t cnt = begin < n ? s.wcnt[wave] : 0u;
-  for (uint32_t e = lane; e < cnt; e += kWave) {
-    const uint64_t k = s.wkey[begin + e];
-    const uint64_t meta = s.wmeta[begin + e];
+  uint32_t cnt[kMaxPack];
+  uint32_t total = 0;
+#pragma unroll
+  for (uint32_t q = 0; q < kMaxPack; ++q) {
+    cnt[q] = q < m && (r0 + q) * s.per_wave < n ? s.wcnt[r0 + q] : 0u;
+    total += cnt[q];
+  }
+  for (uint32_t e = lane; e < total; e += kWave) {
+    // region q with cnt[0] + ... + cnt[q-1] <= e < ... + cnt[q], entry `off` of it
+    uint32_t q = 0, off = e, acc = 0;
+#pragma unroll
+    for (uint32_t u = 0; u + 1 < kMaxPack; ++u) {
+      acc += cnt[u];
+      if (e >= acc) {
+        q = u + 1;
+        off = e - acc;
+      }
+    }
+    const uint64_t r = r0 + q;
+    const uint64_t begin = r * s.per_wave;
+    const uint64_t k = s.wkey[begin + off];
+    const uint64_t meta = s.wmeta[begin + off];
     uint64_t p = mix64(k ^ s.dset_seed) & s.dset_mask;
     bool winner = false;
     for (;;) {
@@ -392,28 +414,42 @@ __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t 
     }
     if (out) out[meta & kIdxMask] = winner ? 1 : 0;
     // remember the scratch-set slot for the scrub (~0: nothing to clear)
-    if (s.dirty) s.dirty[wave * s.dirty_stride + e] = winner ? p : ~0ull;
-    else s.wmeta[begin + e] = winner ? p : ~0ull;
+    if (s.dirty) s.dirty[r * s.dirty_stride + off] = winner ? p : ~0ull;
+    else s.wmeta[begin + off] = winner ? p : ~0ull;
     if (!winner) continue;
     uint64_t y = k;
     uint32_t steps = 0;
     const bool placed = cuckoo_chain<SCRIPTED>(t, y, hidx<SCRIPTED>(t, y, 0), nevict, steps);
     if (!placed) stash_put(t, y);        // y may be another key than the winner's
-    chain_record(t, steps, placed, wave);
+    chain_record(t, steps, placed, r);
     ++nnew;
   }
-  if (s.dirty && lane == 0) s.dirty_cnt[wave] = cnt;
+  if (s.dirty && lane == 0) {
+#pragma unroll
+    for (uint32_t q = 0; q < kMaxPack; ++q)
+      if (q < m) s.dirty_cnt[r0 + q] = cnt[q];
+  }
 }
 
 template <bool SCRIPTED>
+__device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
+                                                    const CuckooScratch& s, uint64_t wave,
+                                                    unsigned long long& nnew, unsigned long long& nevict) {
+  cuckoo_evict_regions<SCRIPTED>(t, n, out, s, wave, 1, nnew, nevict);
+}
+
+// `nregions`: the probe kernel's waves; wave w takes regions w*pack ...
+template <bool SCRIPTED>
 __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64_t n, uint8_t* __restrict__ out,
-                                                               CuckooScratch s) {
+                                                               CuckooScratch s, uint64_t nregions, uint32_t pack) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   unsigned long long nnew = 0, nevict = 0;
-  if (s.dirty && wave == 0 && lane_id() == 0) {
-    s.dirty_desc[0] = (uint64_t)gridDim.x * (kBlock / kWave);
+  if (s.dirty && wave == 0 && lane_id() == 0) s.dirty_desc[0] = nregions;
+  const uint64_t r0 = wave * pack;
+  if (r0 < nregions) {
+    const uint32_t m = (uint32_t)(nregions - r0 < pack ? nregions - r0 : pack);
+    cuckoo_evict_regions<SCRIPTED>(t, n, out, s, r0, m, nnew, nevict);
   }
-  cuckoo_evict_region<SCRIPTED>(t, n, out, s, wave, nnew, nevict);
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);
 }

@@ -331,7 +331,10 @@ __global__ __launch_bounds__(kBlock) void bfs_cuckoo_evict_kernel(DevTable t, ui
       __hip_atomic_fetch_add(&cnt[i], 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
       uint64_t y = k;
       uint32_t steps = 0;
-      if (!cuckoo_chain<false>(t, y, hidx<false>(t, y, 0), nevict, steps)) stash_put(t, y);
+      const uint64_t h1 = hidx<false>(t, y, 0);
+      const bool placed = (t.flags & kFlagLookahead) ? cuckoo_chain<false, true>(t, y, h1, nevict, steps)
+                                                      : cuckoo_chain<false, false>(t, y, h1, nevict, steps);
+      if (!placed) stash_put(t, y);
       ++nnew;
     }
   }

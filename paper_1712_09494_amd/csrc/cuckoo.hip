@@ -66,10 +66,19 @@ hipError_t cuckoo_evict(const DevTable& t, uint64_t n, uint8_t* out, const Cucko
   const uint64_t nregions = (uint64_t)grid * (kBlock / kWave);
   const uint64_t waves = (nregions + pack - 1) / pack;
   const uint32_t g = (uint32_t)((waves + kBlock / kWave - 1) / (kBlock / kWave));
-  if (scripted)
-    hipLaunchKernelGGL((cuckoo_evict_kernel<true>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions, pack);
+  const bool look = (t.flags & kFlagLookahead) != 0;
+  if (scripted && look)
+    hipLaunchKernelGGL((cuckoo_evict_kernel<true, true>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions,
+                       pack);
+  else if (scripted)
+    hipLaunchKernelGGL((cuckoo_evict_kernel<true, false>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions,
+                       pack);
+  else if (look)
+    hipLaunchKernelGGL((cuckoo_evict_kernel<false, true>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions,
+                       pack);
   else
-    hipLaunchKernelGGL((cuckoo_evict_kernel<false>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions, pack);
+    hipLaunchKernelGGL((cuckoo_evict_kernel<false, false>), dim3(g), dim3(kBlock), t.lds, st, t, n, out, s, nregions,
+                       pack);
   return hipGetLastError();
 }
 

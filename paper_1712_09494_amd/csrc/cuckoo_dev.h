@@ -324,11 +324,10 @@ __global__ __launch_bounds__(kBlock) void cuckoo_probe_kernel(DevTable t, const 
 // y at h_j this way keeps the early-exit invariant of the lookups: h_1..h_a
 // are taken (y sat at h_a, which the evicting key now holds) and
 // h_{a+1}..h_{j-1} were seen taken, and slots never empty again.
-template <bool SCRIPTED>
+template <bool SCRIPTED, bool LOOK>
 __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uint64_t slot,
                                              unsigned long long& nevict, uint32_t& steps) {
   const uint32_t c = t.nhash;
-  const bool look = (t.flags & kFlagLookahead) != 0;
   for (uint32_t step = 0;; ++step) {
     const uint64_t old = exch64(&t.slots[slot], x);
     ++steps;
@@ -336,29 +335,52 @@ __device__ __forceinline__ bool cuckoo_chain(const DevTable& t, uint64_t& x, uin
     x = old;
     ++nevict;
     if (step + 1 >= t.max_chain) return false;   // the max_chain-th evicted key goes to the stash
-    // The hash function that placed x here is the last j with h_j(x) == slot;
-    // continue with the next one (cyclically), skipping ones that map here.
-    uint64_t h[kMaxHash];
-    int a = -1;
-    for (uint32_t j = 0; j < c; ++j) {
-      h[j] = hidx<SCRIPTED>(t, x, j);
-      if (h[j] == slot) a = (int)j;
-    }
-    if (look && a + 1 < (int)c) {
-      uint64_t v[kMaxHash];
-      for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) v[j] = h[j] != slot ? t.slots[h[j]] : 0;
-      for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) {
-        if (h[j] != slot && v[j] == kEmpty && cas64(&t.slots[h[j]], kEmpty, x) == kEmpty) return true;
+    if constexpr (LOOK) {
+      uint64_t h[kMaxHash];
+      int a = -1;
+      for (uint32_t j = 0; j < c; ++j) {
+        h[j] = hidx<SCRIPTED>(t, x, j);
+        if (h[j] == slot) a = (int)j;
+      }
+      if (a + 1 < (int)c) {
+        uint64_t v[kMaxHash];
+        for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) v[j] = h[j] != slot ? t.slots[h[j]] : 0;
+        for (uint32_t j = (uint32_t)(a + 1); j < c; ++j) {
+          if (h[j] != slot && v[j] == kEmpty && cas64(&t.slots[h[j]], kEmpty, x) == kEmpty) return true;
+        }
       }
     }
-    uint32_t nj = (uint32_t)(a + 1) % c;
-    uint32_t tries = 0;
-    while (h[nj] == slot && tries < c) {
-      nj = (nj + 1) % c;
-      ++tries;
+    // The hash function that placed x here is the last j with h_j(x) == slot
+    // (a); x continues with h_{a+1}, which maps elsewhere by the choice of a,
+    // or, after h_c (or when none maps here), with the first h_j that maps
+    // elsewhere.  One pass over j, keeping no per-j values, so the kernel
+    // stays within 64 vector registers.
+    int a = -1;
+    bool after = false, have_first = false;
+    uint64_t hnext = 0, hfirst = 0;
+    for (uint32_t j = 0; j < c; ++j) {
+      const uint64_t hj = hidx<SCRIPTED>(t, x, j);
+      if (hj == slot) {
+        a = (int)j;
+        after = true;
+      } else {
+        if (after) {
+          hnext = hj;
+          after = false;
+        }
+        if (!have_first) {
+          hfirst = hj;
+          have_first = true;
+        }
+      }
     }
-    if (h[nj] == slot) return false;   // no other slot for x
-    slot = h[nj];
+    if (a >= 0 && a + 1 < (int)c) {
+      slot = hnext;
+    } else if (have_first) {
+      slot = hfirst;
+    } else {
+      return false;   // no other slot for x
+    }
   }
 }
 
@@ -377,7 +399,7 @@ __device__ __forceinline__ void chain_record(const DevTable& t, uint32_t steps, 
 // fewer keys than a wave has lanes.
 constexpr uint32_t kMaxPack = 8;
 
-template <bool SCRIPTED>
+template <bool SCRIPTED, bool LOOK>
 __device__ __forceinline__ void cuckoo_evict_regions(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
                                                      const CuckooScratch& s, uint64_t r0, uint32_t m,
                                                      unsigned long long& nnew, unsigned long long& nevict) {
@@ -419,7 +441,7 @@ __device__ __forceinline__ void cuckoo_evict_regions(const DevTable& t, uint64_t
     if (!winner) continue;
     uint64_t y = k;
     uint32_t steps = 0;
-    const bool placed = cuckoo_chain<SCRIPTED>(t, y, hidx<SCRIPTED>(t, y, 0), nevict, steps);
+    const bool placed = cuckoo_chain<SCRIPTED, LOOK>(t, y, hidx<SCRIPTED>(t, y, 0), nevict, steps);
     if (!placed) stash_put(t, y);        // y may be another key than the winner's
     chain_record(t, steps, placed, r);
     ++nnew;
@@ -431,15 +453,15 @@ __device__ __forceinline__ void cuckoo_evict_regions(const DevTable& t, uint64_t
   }
 }
 
-template <bool SCRIPTED>
+template <bool SCRIPTED, bool LOOK>
 __device__ __forceinline__ void cuckoo_evict_region(const DevTable& t, uint64_t n, uint8_t* __restrict__ out,
                                                     const CuckooScratch& s, uint64_t wave,
                                                     unsigned long long& nnew, unsigned long long& nevict) {
-  cuckoo_evict_regions<SCRIPTED>(t, n, out, s, wave, 1, nnew, nevict);
+  cuckoo_evict_regions<SCRIPTED, LOOK>(t, n, out, s, wave, 1, nnew, nevict);
 }
 
 // `nregions`: the probe kernel's waves; wave w takes regions w*pack ...
-template <bool SCRIPTED>
+template <bool SCRIPTED, bool LOOK>
 __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64_t n, uint8_t* __restrict__ out,
                                                                CuckooScratch s, uint64_t nregions, uint32_t pack) {
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
@@ -448,7 +470,7 @@ __global__ __launch_bounds__(kBlock) void cuckoo_evict_kernel(DevTable t, uint64
   const uint64_t r0 = wave * pack;
   if (r0 < nregions) {
     const uint32_t m = (uint32_t)(nregions - r0 < pack ? nregions - r0 : pack);
-    cuckoo_evict_regions<SCRIPTED>(t, n, out, s, r0, m, nnew, nevict);
+    cuckoo_evict_regions<SCRIPTED, LOOK>(t, n, out, s, r0, m, nnew, nevict);
   }
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
   wave_count(t.ctr->evictions, nevict, (uint32_t)wave);

@@ -111,7 +111,10 @@ __global__ __launch_bounds__(kBlock) void multi_cuckoo_evict_kernel(const MultiC
     const uint64_t it = uniform_item(items, idx);
     const MultiCuckoo& m = tabs[(uint32_t)(it >> 40)];
     unsigned long long nnew = 0, nevict = 0;
-    cuckoo_evict_region<false>(m.t, m.n, m.out, m.s, it & kRegionMask, nnew, nevict);
+    if (m.t.flags & kFlagLookahead)
+      cuckoo_evict_region<false, true>(m.t, m.n, m.out, m.s, it & kRegionMask, nnew, nevict);
+    else
+      cuckoo_evict_region<false, false>(m.t, m.n, m.out, m.s, it & kRegionMask, nnew, nevict);
     wave_count(m.t.ctr->size, nnew, (uint32_t)(wave + idx));
     wave_count(m.t.ctr->evictions, nevict, (uint32_t)(wave + idx));
   }

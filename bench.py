@@ -699,9 +699,10 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
             c = 4 if (kind == "cuckoo" and lf > 0.85) else 3
             kw = dict(bucket_slots=args.bucket_slots) if kind == "bucketed" else {}
             t = b.Table(kind, capacity=cap, nhash=c, max_batch=1 << 24, **kw)
-            for s0 in range(0, args.n, 1 << 20):        # untimed first fill of the fresh table
-                t.find_or_put(keys[s0:s0 + (1 << 20)], out[s0:s0 + (1 << 20)])
             for batch in (1 << 16, 1 << 20, 1 << 24):
+                t.clear()
+                for s0 in range(0, args.n, batch):            # untimed fill at this batch size
+                    t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
                 t.clear()
                 evs = []
                 for s0 in range(0, args.n, batch):

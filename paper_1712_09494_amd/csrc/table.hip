@@ -475,9 +475,11 @@ static int vec_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_
 
 // Regions of the probe kernel whose listed keys one wave of the evict kernel
 // serves as one list.  Near the end of a fill a region lists about half as
-// many keys as a wave has lanes; two per wave cut the evict kernel of the
-// 2^20-key batches of a 2^26-key fill from 33.7 to 29.7 us on average (c = 4;
-// three per wave: 30.5, four: 31.0, eight: 35.0).
+// many keys as a wave has lanes.  With a probe grid of 8 blocks per compute
+// unit, two per wave cut the evict kernel of the 2^20-key batches of a
+// 2^26-key fill from 33.7 to 29.7 us on average (c = 4; three: 30.5, four:
+// 31.0, eight: 35.0); with the probe grid of 6 blocks per unit, one and two
+// per wave give the same fill time (5.92 ms; three: 6.02, four: 6.07).
 constexpr uint32_t kEvictPack = 2;
 
 int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStream_t s,

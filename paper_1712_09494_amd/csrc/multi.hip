@@ -220,6 +220,12 @@ uint64_t multi_chunk(uint64_t total, uint64_t max_waves) {
   return c;
 }
 
+// Grid cap of the Cuckoo phases: three quarters of `max_blocks` (6 blocks
+// per compute unit), as for the single-table Cuckoo probe; 256 tables of
+// 2^6..2^26 slots in one plan launch: 8.8-8.9 ms at 8 blocks per unit,
+// 8.05-8.19 at 6, 7.95 at 5, 8.04 at 4.
+static uint32_t cuckoo_blocks(uint32_t max_blocks) { return max_blocks / 4 * 3 ? max_blocks / 4 * 3 : 1; }
+
 uint32_t multi_grid(uint64_t nitems, uint32_t max_blocks) {
   const uint64_t blocks = (nitems + (kBlock / kWave) - 1) / (kBlock / kWave);
   return (uint32_t)(blocks < max_blocks ? (blocks ? blocks : 1) : max_blocks);
@@ -351,15 +357,17 @@ hipError_t multi_plan_build(const std::vector<MultiSpec>& specs, const std::vect
   std::vector<uint64_t> items(cap_b);
   std::vector<MultiCuckoo> ctabs(nc);
   std::vector<uint64_t> citems(cap_c);
+  const uint32_t cmb = cuckoo_blocks(max_blocks);
   const uint64_t nit = fill_bucketed(specs.data(), nt, max_waves, tabs.data(), items.data(), cap_b);
-  const uint64_t ncit = fill_cuckoo(cspecs.data(), nc, max_waves, ctabs.data(), citems.data(), cap_c);
+  const uint64_t ncit = fill_cuckoo(cspecs.data(), nc, (uint64_t)cmb * (kBlock / kWave), ctabs.data(), citems.data(),
+                                    cap_c);
   if (nit == ~0ull || ncit == ~0ull) return hipErrorInvalidValue;
   items.resize(nit);
   citems.resize(ncit);
   plan.nitems = (uint32_t)items.size();
   plan.ncitems = (uint32_t)citems.size();
   plan.grid = multi_grid(plan.nitems, max_blocks);
-  plan.cgrid = multi_grid(plan.ncitems, max_blocks);
+  plan.cgrid = multi_grid(plan.ncitems, cmb);
   const size_t b_tabs = align256(sizeof(MultiTable) * nt);
   const size_t b_items = align256(items.size() * 8);
   const size_t b_ctabs = align256(sizeof(MultiCuckoo) * nc);
@@ -451,8 +459,10 @@ hipError_t multi_dyn_issue(MultiDyn& d, const MultiSpec* specs, uint32_t nt, con
   const size_t o_ctabs = o;
   o += align256(sizeof(MultiCuckoo) * nc);
   const size_t o_citems = o;
-  const uint64_t ncit = fill_cuckoo(cspecs, nc, max_waves, reinterpret_cast<MultiCuckoo*>(h + o_ctabs),
-                                    reinterpret_cast<uint64_t*>(h + o), d.cap_items);
+  const uint32_t cmb = cuckoo_blocks(max_blocks);
+  const uint64_t ncit = fill_cuckoo(cspecs, nc, (uint64_t)cmb * (kBlock / kWave),
+                                    reinterpret_cast<MultiCuckoo*>(h + o_ctabs), reinterpret_cast<uint64_t*>(h + o),
+                                    d.cap_items);
   if (ncit == ~0ull) return hipErrorInvalidValue;
   o += align256(ncit * 8);
   const size_t o_qtabs = o;
@@ -466,7 +476,7 @@ hipError_t multi_dyn_issue(MultiDyn& d, const MultiSpec* specs, uint32_t nt, con
                        reinterpret_cast<const MultiTable*>(dv + o_tabs),
                        reinterpret_cast<const uint64_t*>(dv + o_items), (uint32_t)nit);
   if (ncit) {
-    const dim3 g(multi_grid(ncit, max_blocks)), b(kBlock);
+    const dim3 g(multi_grid(ncit, cmb)), b(kBlock);
     const MultiCuckoo* ct = reinterpret_cast<const MultiCuckoo*>(dv + o_ctabs);
     const uint64_t* ci = reinterpret_cast<const uint64_t*>(dv + o_citems);
     hipLaunchKernelGGL(multi_cuckoo_probe_kernel, g, b, 0, s, ct, ci, (uint32_t)ncit);

@@ -433,7 +433,8 @@ def headline(res: dict) -> dict:
                 e["admission"] = {kk: v["admission"][kk] for kk in ("throttled", "latency_ms_p99", "requests_per_s")}
             served_sum[k] = e
     w1 = res.get("w1")
-    w1_sum = {k: [v["fop_mops"], v.get("frac_of_mix")] for k, v in w1["designs"].items()} if w1 else None
+    w1_sum = ({k: [v["fop_mops"], v.get("query_mops"), v.get("frac_of_mix")] for k, v in w1["designs"].items()}
+              if w1 else None)
     ev = res.get("cuckoo_evict")
     evl = res.get("cuckoo_evict_lookahead")
     line = {
@@ -462,7 +463,7 @@ def headline(res: dict) -> dict:
                                     chains=[(e.get("chains") or {}).get(k) for k in ("mean", "p99", "max")])
                          for name, e in (("chain", ev), ("lookahead", evl)) if e} or None,
         "sweep_fop_mops_b16_b20_b24": sweep_sum,
-        "w1_fop_mops_frac_of_mix": w1_sum,
+        "w1_fop_query_mops_frac_of_mix": w1_sum,
         "bfs": bfs_sum,
         "batched": batched_sum,
         "served": served_sum,
@@ -798,7 +799,12 @@ def run_w1(b, inputs, torch, dev, stream):
     line16 = line_probe_rate(b, torch, dev, stream, slots)
     res = {"keys": int(ins.size), "slots": slots, "cache_resident": True, "line_probe_16MiB_Gps": line16,
            "designs": {}}
+    # bucketed: lane-group find-or-put (queries one lane per key, the
+    # default), the same with the lane-group query of Sec. 4.2, and one lane
+    # per key for both
     for name, kind, kw in (("bucketed", "bucketed", dict(bucket_slots=8)),
+                           ("bucketed_group_query", "bucketed",
+                            dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY)),
                            ("bucketed_one_lane", "bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
                            ("cuckoo", "cuckoo", {})):
         t = b.Table(kind, capacity=slots, nhash=3, **kw)

@@ -9,6 +9,7 @@ of include/ht.h; ``binding`` is the thin Python layer over it.
 from .binding import (  # noqa: F401
     EMPTY, HT_BUCKETED, HT_CUCKOO, HT_EFULL, HT_EHIP, HT_EINVAL, HT_ENOMEM, HT_OK,
     HT_FLAG_BUCKETED_ATOMIC_LOADS, HT_FLAG_CUCKOO_PAPER_ORDER, HT_FLAG_SCRIPTED_HASH,
-    HT_FLAG_BUCKETED_PAPER_FULL,
+    HT_FLAG_BUCKETED_PAPER_FULL, HT_FLAG_BUCKETED_ONE_LANE, HT_FLAG_BUCKETED_GROUP_QUERY, HT_FLAG_CHAIN_STATS,
+    HT_FLAG_CUCKOO_LOOKAHEAD, HT_FLAG_CUCKOO_SINGLE_PASS,
     HtError, HtLibraryMissing, MultiPlan, Server, Table, find_or_put_multi, load, u64,
 )

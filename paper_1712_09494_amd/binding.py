@@ -39,6 +39,7 @@ HT_FLAG_CUCKOO_SINGLE_PASS = 1 << 4
 HT_FLAG_BUCKETED_ONE_LANE = 1 << 5
 HT_FLAG_CHAIN_STATS = 1 << 6
 HT_FLAG_CUCKOO_LOOKAHEAD = 1 << 7
+HT_FLAG_BUCKETED_GROUP_QUERY = 1 << 8
 
 EMPTY = (1 << 64) - 1
 

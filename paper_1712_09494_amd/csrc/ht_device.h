@@ -27,6 +27,7 @@ constexpr int kChainBins = 64;       // eviction-chain histogram bins
 // Table flags the kernels read (same values as the HT_FLAG_* of the C ABI).
 constexpr uint32_t kFlagChainStats = 1u << 6;
 constexpr uint32_t kFlagLookahead = 1u << 7;
+constexpr uint32_t kFlagGroupQuery = 1u << 8;
 
 // Hash family: h_j(k) = floor(mix64(k ^ s_j) * range / 2^64).
 // mix64 is the splitmix64 finalizer (Steele, Lea & Flood 2014), a bijection

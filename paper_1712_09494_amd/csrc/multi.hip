@@ -185,6 +185,11 @@ __global__ __launch_bounds__(kBlock) void multi_query_kernel(const MultiQuery* _
           m.out[i] = h ? 1 : 0;
         }
       }
+    } else if (!(m.t.flags & kFlagGroupQuery)) {
+      for (uint64_t base = begin; base < end; base += kWave) {
+        const uint64_t i = base + lane;
+        if (i < end) m.out[i] = (uint8_t)lane_query<false>(m.t, m.keys[i], sc, oc);
+      }
     } else {
       const uint32_t L = m.t.bucket_slots / 2;
       const uint32_t G = kWave / L;
@@ -292,10 +297,11 @@ static uint64_t fill_cuckoo(const MultiCuckooSpec* cs, uint32_t nc, uint64_t max
 }
 
 // Keys one wave answers per turn of the many-table query: 64 (a key per
-// lane) for a Cuckoo table, two per lane group of B/2 lanes for a bucketed
-// one.
+// lane) for a Cuckoo table and a bucketed one queried one lane per key, two
+// per lane group of B/2 lanes for a bucketed one with group queries.
 static uint64_t query_turn(const MultiQuerySpec& q) {
-  return q.cuckoo ? (uint64_t)kWave : 2ull * (kWave / (q.t.bucket_slots / 2));
+  if (q.cuckoo || !(q.t.flags & kFlagGroupQuery)) return kWave;
+  return 2ull * (kWave / (q.t.bucket_slots / 2));
 }
 
 bool multi_query_alone(const MultiQuerySpec& q, uint32_t max_blocks) {

@@ -323,7 +323,8 @@ int validate_config(const ht_config* c) {
     return fail(HT_EINVAL, "keys_per_group must be 0, 1, 2 or 4");
   if (c->flags & ~(uint32_t)(HT_FLAG_CUCKOO_PAPER_ORDER | HT_FLAG_BUCKETED_ATOMIC_LOADS | HT_FLAG_SCRIPTED_HASH |
                              HT_FLAG_BUCKETED_PAPER_FULL | HT_FLAG_CUCKOO_SINGLE_PASS |
-                             HT_FLAG_BUCKETED_ONE_LANE | HT_FLAG_CHAIN_STATS | HT_FLAG_CUCKOO_LOOKAHEAD))
+                             HT_FLAG_BUCKETED_ONE_LANE | HT_FLAG_CHAIN_STATS | HT_FLAG_CUCKOO_LOOKAHEAD |
+                             HT_FLAG_BUCKETED_GROUP_QUERY))
     return fail(HT_EINVAL, "unknown flag bits");
   if ((c->flags & HT_FLAG_CUCKOO_LOOKAHEAD) && (c->flags & HT_FLAG_CUCKOO_PAPER_ORDER))
     return fail(HT_EINVAL, "the lookahead flag changes the paper-order insertion; use one of them");
@@ -566,7 +567,10 @@ int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStr
   }
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
-  if (t->cfg.kind == HT_BUCKETED && (t->cfg.flags & HT_FLAG_BUCKETED_ONE_LANE)) {
+  // bucketed: one lane per key unless the table asks for the lane groups of
+  // Sec. 4.2 (same answers; one lane per key is faster at every bucket width)
+  if (t->cfg.kind == HT_BUCKETED &&
+      ((t->cfg.flags & HT_FLAG_BUCKETED_ONE_LANE) || !(t->cfg.flags & HT_FLAG_BUCKETED_GROUP_QUERY))) {
     const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
     KernelTimer kt("bucketed_lane_query", s);
     HT_HIP(bucketed_lane_query(d, keys, n, out, (uint32_t)blocks, scripted, s));

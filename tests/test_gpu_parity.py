@@ -34,9 +34,13 @@ DESIGNS = {
     "bkt64_lane": dict(kind="bucketed", bucket_slots=64, flags=b.HT_FLAG_BUCKETED_ONE_LANE),
     "cuckoo_lds64k": dict(kind="cuckoo", lds_bytes=65536),
     "cuckoo_look": dict(kind="cuckoo", flags=b.HT_FLAG_CUCKOO_LOOKAHEAD),
+    # queries with the lane groups of Sec. 4.2 (default: one lane per key)
+    "bkt8_groupq": dict(kind="bucketed", bucket_slots=8, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY),
+    "bkt16_groupq": dict(kind="bucketed", bucket_slots=16, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY),
+    "bkt64_groupq": dict(kind="bucketed", bucket_slots=64, keys_per_group=4, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY),
 }
-MAIN = ["bkt16", "bkt8", "bkt16_atomic", "cuckoo", "cuckoo_paper", "cuckoo_look"]
-MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4", "bkt8_lane"]
+MAIN = ["bkt16", "bkt8", "bkt16_atomic", "cuckoo", "cuckoo_paper", "cuckoo_look", "bkt8_groupq"]
+MORE = ["bkt16_r1", "bkt8_r4", "cuckoo_r1", "cuckoo_r4", "bkt8_lane", "bkt16_groupq"]
 
 
 def dev(a):
@@ -128,7 +132,7 @@ def test_random_small_tables(design):
         t.close()
 
 
-@pytest.mark.parametrize("design", MAIN + MORE + ["bkt32", "bkt64", "bkt64_r4"])
+@pytest.mark.parametrize("design", MAIN + MORE + ["bkt32", "bkt64", "bkt64_r4", "bkt64_groupq"])
 def test_small_workload_2p20(design):
     """2^20 distinct keys at load factor 0.5, then 2^20 queries half present."""
     ins, q = inputs.small_workload()

@@ -20,6 +20,8 @@ KINDS = [
     ("bucketed", dict(bucket_slots=64, nhash=4)),
     ("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
     ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)),
+    ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY)),
+    ("bucketed", dict(bucket_slots=64, nhash=4, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY)),
     ("cuckoo", dict()),
     ("cuckoo", dict(nhash=4)),
     ("cuckoo", dict(flags=b.HT_FLAG_CUCKOO_PAPER_ORDER)),
@@ -80,7 +82,8 @@ def test_query_multi_matches_single_queries_large():
     small ones that share a launch."""
     tables, oracles, queries = [], [], []
     for i, (kind, kw) in enumerate([("bucketed", dict(bucket_slots=16)), ("cuckoo", dict()),
-                                    ("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE))]):
+                                    ("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+                                    ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_GROUP_QUERY))]):
         n = (1 << 21) + 4097 * (i + 1)
         keys = inputs.random_sequence(n, int(0.8 * n), seed=40 + i)
         t = b.Table(kind, capacity=n * 5 // 4, nhash=3, **kw)

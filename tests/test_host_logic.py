@@ -122,7 +122,7 @@ def _fake_result():
                                     "p99": 31, "max": 127}},
         "sweep": sweep,
         "w1": {"designs": {k: {"fop_mops": 15900.0, "query_mops": 36000.0, "frac_of_mix": 0.6}
-                           for k in ("bucketed", "bucketed_one_lane", "cuckoo")}},
+                           for k in ("bucketed", "bucketed_group_query", "bucketed_one_lane", "cuckoo")}},
         "bfs": {"designs": {k: {"fop_mops": 32600.0, "level_mops": 13300.0}
                             for k in ("bucketed", "bucketed_one_lane", "bucketed_fused", "cuckoo", "cuckoo_fused",
                                       "bucketed_b16", "cuckoo_paper_order")}},

@@ -25,6 +25,7 @@ detail file (--detail) and progress to stderr.
 from __future__ import annotations
 
 import argparse
+import gc
 import json
 import os
 import sys
@@ -97,6 +98,11 @@ def main():
     from paper_1712_09494_amd import inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    # no automatic garbage collection: a collection pass inside a timed loop
+    # stalls the host between an event and the launch it brackets; sections
+    # collect explicitly before they time anything
+    gc.collect()
+    gc.disable()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     b.load()
@@ -107,19 +113,27 @@ def main():
     if any(only.values()):
         res = {}
         if args.probes:
+            gc.collect()
             res["probes"] = run_probes(b, torch, dev, stream)
         if args.bfs_only:
+            gc.collect()
             res["bfs"] = run_bfs(b, inputs, torch)
         if args.served_only:
+            gc.collect()
             res["served"] = run_served(b, inputs, torch, dev, args.served_requests)
         if args.dup_sweep_only:
+            gc.collect()
             res["w1"] = run_w1(b, inputs, torch, dev, stream)
+            gc.collect()
             res["duplication_sweep"] = run_dup_sweep(b, inputs, torch, dev, stream)
         if args.single_pass_only:
+            gc.collect()
             res["single_pass_ablation"] = run_single_pass(b, inputs, torch, dev, stream)
         if args.vectors_only:
+            gc.collect()
             res["vectors"] = run_vectors(b, inputs, torch, dev, stream)
         if args.batched_only:
+            gc.collect()
             res["batched"] = run_batched(b, inputs, torch, dev, stream)
         write_detail(args.detail, res)
         print(json.dumps(res), flush=True)
@@ -205,6 +219,7 @@ def main():
     # add gaps between launches, so they stay out of the per-design figures)
     def per_batch_times(t):
         t.clear()
+        gc.collect()
         evs = []
         for s0 in range(0, args.n, args.batch):
             s1 = min(args.n, s0 + args.batch)
@@ -307,8 +322,10 @@ def main():
                 f"stash {r['stash']}")
 
     if not args.no_sweep:
+        gc.collect()
         res["sweep"] = run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out)
     if not args.no_lds:
+        gc.collect()
         res["lds_ablation"] = run_lds_ablation(b, torch, stream, args, d, keys, out)
     for t in tables.values():
         t.close()
@@ -317,17 +334,24 @@ def main():
     torch.cuda.empty_cache()
 
     if not args.no_dup_sweep:
+        gc.collect()
         res["w1"] = run_w1(b, inputs, torch, dev, stream)
+        gc.collect()
         res["duplication_sweep"] = run_dup_sweep(b, inputs, torch, dev, stream)
     if not args.no_single_pass:
+        gc.collect()
         res["single_pass_ablation"] = run_single_pass(b, inputs, torch, dev, stream)
     if not args.no_vectors:
+        gc.collect()
         res["vectors"] = run_vectors(b, inputs, torch, dev, stream)
     if not args.no_batched:
+        gc.collect()
         res["batched"] = run_batched(b, inputs, torch, dev, stream)
     if not args.no_bfs:
+        gc.collect()
         res["bfs"] = run_bfs(b, inputs, torch)
     if not args.no_served:
+        gc.collect()
         res["served"] = run_served(b, inputs, torch, dev, args.served_requests)
     if not args.no_cpu:
         res["cpu_baseline"] = cpu_baseline(seq, args.batch)
@@ -705,6 +729,7 @@ def run_sweep(b, inputs, torch, dev, stream, args, seq, d, keys, out):
                 for s0 in range(0, args.n, batch):            # untimed fill at this batch size
                     t.find_or_put(keys[s0:s0 + batch], out[s0:s0 + batch])
                 t.clear()
+                gc.collect()
                 evs = []
                 for s0 in range(0, args.n, batch):
                     s1 = min(args.n, s0 + batch)

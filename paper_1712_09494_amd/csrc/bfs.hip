@@ -488,7 +488,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       // the probe grid of the single-table Cuckoo find-or-put (fused levels of
       // the 7-level workload: 36.3-38.6 ms at 8 blocks per compute unit, 32.9
       // at 6)
-      const uint32_t g2 = (uint32_t)std::min<uint64_t>((ngroups + 3) / 4, cuckoo_probe_blocks(t));
+      const uint32_t g2 = (uint32_t)std::min<uint64_t>((ngroups + 3) / 4, atomic_grid_blocks(t));
       HT_HIP(hipEventRecord(ev[2], s));
       HT_HIP(hipEventRecord(ev[6], s));
       hipLaunchKernelGGL(bfs_cuckoo_probe_kernel, dim3(g2), dim3(kBlock), 0, s, m, dt, fr, nf, off, sc, gc, cnt, mk);

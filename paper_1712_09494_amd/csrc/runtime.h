@@ -64,7 +64,7 @@ int fail(int code, const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 uint32_t device_cus(int dev);
 uint32_t max_blocks(const ht_table* t);
-uint32_t cuckoo_probe_blocks(const ht_table* t);
+uint32_t atomic_grid_blocks(const ht_table* t);
 bool is_scripted(const ht_table* t);
 int check_table(const ht_table* t);
 int reserve_scratch(ht_table* t, uint64_t n);

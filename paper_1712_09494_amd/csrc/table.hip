@@ -169,13 +169,16 @@ namespace ht_rt {
 
 uint32_t max_blocks(const ht_table* t) { return t->cus * 8; }
 
-// Grid of the single-table Cuckoo probe kernel: 6 blocks (24 waves) per
-// compute unit, which keeps fewer random reads and compare-and-swaps queued
-// at the memory than the full 8.  Measured on the 2^20-key batches of a
+// Grid of the one-lane-per-key kernels that mix random reads with
+// compare-and-swaps (the Cuckoo probe phases, the state-vector kernels): 6
+// blocks (24 waves) per compute unit, which keeps fewer requests queued at
+// the memory than the full 8.  Measured on the 2^20-key batches of a
 // 2^26-key fill at c = 4 (probe kernel, average per launch): 73.9 us at 8
-// blocks per unit, 67.7 at 7, 66.6 at 6, 70.2 at 5, 67.5 at 4.  The bucketed
-// kernel is fastest at 8 (fill 3.88 ms at 8, 4.05 at 7, 4.33 at 6).
-uint32_t cuckoo_probe_blocks(const ht_table* t) { return t->cus * 6; }
+// blocks per unit, 67.7 at 7, 66.6 at 6, 70.2 at 5, 67.5 at 4; 2^24 state
+// vectors in batches of 2^20: 5-7% faster at 6 than at 8 for both designs
+// and W = 2, 4.  The bucketed lane-group kernel is fastest at 8 (fill 3.88 ms
+// at 8, 4.05 at 7, 4.33 at 6).
+uint32_t atomic_grid_blocks(const ht_table* t) { return t->cus * 6; }
 
 bool is_scripted(const ht_table* t) { return (t->cfg.flags & HT_FLAG_SCRIPTED_HASH) != 0; }
 
@@ -271,7 +274,7 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   // <= 256 below its full grid, n / waves at it) and its count per wave for
   // the deferred scrub, and a word with the record's wave count
   const bool defer = t->cfg.kind == HT_CUCKOO && t->cfg.key_words <= 1;
-  const uint64_t pw = (uint64_t)cuckoo_probe_blocks(t) * (kBlock / kWave);
+  const uint64_t pw = (uint64_t)atomic_grid_blocks(t) * (kBlock / kWave);
   const uint64_t stride = std::max<uint64_t>(256, (n + pw - 1) / pw);
   const size_t b_rec = align_up(nw * stride * 8, 256);
   const size_t b_defer = defer ? b_dset + b_rec + b_c + 256 : 0;
@@ -439,7 +442,7 @@ CuckooScratch scratch_view(const ht_table* t, uint64_t n) {
 // Launch shape of the one-lane-per-key kernels: blocks and keys per wave.
 static void lane_grid(const ht_table* t, uint64_t n, uint32_t keys_per_lane, uint64_t& blocks, uint64_t& per_wave) {
   const uint64_t waves_needed = (n + (uint64_t)kWave * keys_per_lane - 1) / ((uint64_t)kWave * keys_per_lane);
-  blocks = std::min<uint64_t>((waves_needed + 3) / 4, max_blocks(t));
+  blocks = std::min<uint64_t>((waves_needed + 3) / 4, atomic_grid_blocks(t));
   const uint64_t nwaves = blocks * 4;
   per_wave = (n + nwaves - 1) / nwaves;
 }
@@ -529,7 +532,7 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     sc.dirty_stride = t->dirty_stride;
   }
   const uint64_t waves_needed = (n + (uint64_t)kWave * R - 1) / ((uint64_t)kWave * R);
-  const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, cuckoo_probe_blocks(t));
+  const uint64_t blocks = std::min<uint64_t>((waves_needed + 3) / 4, atomic_grid_blocks(t));
   const uint64_t nwaves = blocks * 4;
   sc.per_wave = (n + nwaves - 1) / nwaves;
   if (sc.dirty && sc.per_wave > sc.dirty_stride) {

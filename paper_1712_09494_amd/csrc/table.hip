@@ -170,14 +170,16 @@ namespace ht_rt {
 uint32_t max_blocks(const ht_table* t) { return t->cus * 8; }
 
 // Grid of the one-lane-per-key kernels that mix random reads with
-// compare-and-swaps (the Cuckoo probe phases, the state-vector kernels): 6
+// compare-and-swaps (the Cuckoo probe phases, the state-vector kernels, the
+// one-lane bucketed find-or-put and fused BFS levels): 6
 // blocks (24 waves) per compute unit, which keeps fewer requests queued at
 // the memory than the full 8.  Measured on the 2^20-key batches of a
 // 2^26-key fill at c = 4 (probe kernel, average per launch): 73.9 us at 8
 // blocks per unit, 67.7 at 7, 66.6 at 6, 70.2 at 5, 67.5 at 4; 2^24 state
 // vectors in batches of 2^20: 5-7% faster at 6 than at 8 for both designs
 // and W = 2, 4.  The bucketed lane-group kernel is fastest at 8 (fill 3.88 ms
-// at 8, 4.05 at 7, 4.33 at 6).
+// at 8, 4.05 at 7, 4.33 at 6), and so is the many-table bucketed fill (256
+// tables: 5.73 ms at 8, 5.92 at 6).
 uint32_t atomic_grid_blocks(const ht_table* t) { return t->cus * 6; }
 
 bool is_scripted(const ht_table* t) { return (t->cfg.flags & HT_FLAG_SCRIPTED_HASH) != 0; }
@@ -496,7 +498,8 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
   const bool scripted = is_scripted(t);
   const uint32_t R = t->cfg.keys_per_group;
   if (t->cfg.kind == HT_BUCKETED && (t->cfg.flags & HT_FLAG_BUCKETED_ONE_LANE)) {
-    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, max_blocks(t));
+    // W2 fill: 4.08 ms at 8 blocks per compute unit, 3.72 at 6, 3.90 at 4
+    const uint64_t blocks = std::min<uint64_t>((n + kBlock - 1) / kBlock, atomic_grid_blocks(t));
     KernelTimer kt("bucketed_lane_fop", s);
     HT_HIP(bucketed_lane_find_or_put(d, keys, n, out, (uint32_t)blocks, scripted, s));
     return HT_OK;

@@ -8,7 +8,7 @@
 #include "runtime.h"
 
 namespace ht {
-hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
+hipError_t fill_words(uint64_t*, uint64_t, uint64_t, hipStream_t);
 }  // namespace ht
 
 using namespace ht;
@@ -89,6 +89,6 @@ extern "C" int ht_find_or_put_noalloc(ht_table* t, const uint64_t* d_keys, uint6
   // call on this device left, so the part this call uses is filled first (a
   // fill kernel: no memset node when the caller captures a graph).  The lists
   // and counts are written before they are read.
-  HT_HIP(fill_words(sc.dset, sc.dset_mask + 1, kEmpty, max_blocks(t), s));
+  HT_HIP(fill_words(sc.dset, sc.dset_mask + 1, kEmpty, s));
   return do_find_or_put(t, d_keys, n, d_out_is_new, s, &sc);
 }

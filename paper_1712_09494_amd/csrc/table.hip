@@ -39,7 +39,7 @@ hipError_t vec_commit(const DevTable&, const uint64_t*, uint64_t, const CuckooSc
 hipError_t vec_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, hipStream_t);
 hipError_t vec_dump(const uint64_t*, uint64_t, const uint64_t*, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                     uint32_t, hipStream_t);
-hipError_t fill_words(uint64_t*, uint64_t, uint64_t, uint32_t, hipStream_t);
+hipError_t fill_words(uint64_t*, uint64_t, uint64_t, hipStream_t);
 hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t compact_words(const uint64_t*, uint64_t, uint64_t*, uint64_t, unsigned long long*, uint32_t,
                          hipStream_t);
@@ -232,11 +232,10 @@ int alloc_storage(ht_table* t) {
 }
 
 int clear_async(ht_table* t, hipStream_t s) {
-  const uint32_t g = max_blocks(t);
   KernelTimer kt("clear", s);
-  HT_HIP(fill_words(t->dev.slots, t->nslots, kEmpty, g, s));
-  HT_HIP(fill_words(t->dev.stash, t->dev.stash_slots, kEmpty, g, s));
-  HT_HIP(fill_words(t->dev.overflow, t->dev.overflow_slots, kEmpty, g, s));
+  HT_HIP(fill_words(t->dev.slots, t->nslots, kEmpty, s));
+  HT_HIP(fill_words(t->dev.stash, t->dev.stash_slots, kEmpty, s));
+  HT_HIP(fill_words(t->dev.overflow, t->dev.overflow_slots, kEmpty, s));
   HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->dev.ctr), sizeof(Counters) / 4, s));
   return HT_OK;
 }
@@ -301,9 +300,9 @@ int reserve_scratch(ht_table* t, uint64_t n) {
   }
   t->dset_slots = ds;
   t->scratch_n = n;
-  HT_HIP(fill_words(t->dset, ds, kEmpty, max_blocks(t), nullptr));
+  HT_HIP(fill_words(t->dset, ds, kEmpty, nullptr));
   if (defer) {
-    HT_HIP(fill_words(t->dset_defer, ds, kEmpty, max_blocks(t), nullptr));
+    HT_HIP(fill_words(t->dset_defer, ds, kEmpty, nullptr));
     HT_HIP(zero_words(reinterpret_cast<uint32_t*>(t->dirty_desc), 4, nullptr));   // no record yet
   }
   HT_HIP(hipDeviceSynchronize());

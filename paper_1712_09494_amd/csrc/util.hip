@@ -5,9 +5,20 @@
 
 namespace ht {
 
+// n words of value v from p: 16-byte stores over the 16-byte aligned pairs,
+// 8-byte stores for a leading and a trailing odd word.
 __global__ __launch_bounds__(kBlock) void fill_kernel(uint64_t* __restrict__ p, uint64_t n, uint64_t v) {
   const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < n; i += stride) p[i] = v;
+  const uint64_t first = (uint64_t)blockIdx.x * kBlock + threadIdx.x;
+  const uint64_t head = (reinterpret_cast<uintptr_t>(p) & 15) ? 1 : 0;   // p is 8-byte aligned
+  const uint64_t pairs = (n - (head < n ? head : n)) / 2;
+  ulonglong2* q = reinterpret_cast<ulonglong2*>(p + head);
+  const ulonglong2 vv = make_ulonglong2(v, v);
+  for (uint64_t i = first; i < pairs; i += stride) q[i] = vv;
+  if (first == 0) {
+    if (head && n) p[0] = v;
+    if (head + 2 * pairs < n) p[n - 1] = v;
+  }
 }
 
 __global__ void zero_words_kernel(uint32_t* __restrict__ p, uint64_t nwords) {
@@ -37,10 +48,14 @@ __global__ __launch_bounds__(kBlock) void compact_kernel(const uint64_t* __restr
   }
 }
 
-hipError_t fill_words(uint64_t* p, uint64_t n, uint64_t v, uint32_t grid, hipStream_t s) {
+// A fill writes each 16-byte pair once with a thread per pair, up to 2^17
+// blocks (then a few pairs per thread).  Clearing a 0.69 GB table: 0.110 ms
+// (6.2 TB/s) against 0.164 ms for 8-byte stores from a persistent grid of 8
+// blocks per compute unit, 0.130 ms for 8-byte stores from 2^17 blocks.
+hipError_t fill_words(uint64_t* p, uint64_t n, uint64_t v, hipStream_t s) {
   if (n == 0) return hipSuccess;
-  uint64_t need = (n + kBlock - 1) / kBlock;
-  const uint32_t g = (uint32_t)(need < grid ? need : grid);
+  const uint64_t need = (n / 2 + kBlock - 1) / kBlock + 1;
+  const uint32_t g = (uint32_t)(need < (1u << 17) ? need : (1u << 17));
   hipLaunchKernelGGL(fill_kernel, dim3(g), dim3(kBlock), 0, s, p, n, v);
   return hipGetLastError();
 }

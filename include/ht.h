@@ -102,7 +102,7 @@ enum {
    * batch can then be stored twice and reported new more than once (a lookup
    * misses a copy that another thread holds in flight); exact only for
    * batches without repeated keys.  Not combinable with key_words > 1.  The
-   * many-table call and the serving engine always use the exact three-kernel
+   * many-table call and the serving engine always use the exact three-phase
    * insertion. */
   HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4,
   /* Bucketed, single-word keys: probe with one lane per key (each lane reads
@@ -205,14 +205,20 @@ int ht_destroy(ht_table* t);
  * vectors of W words each, row-major (n * W words, 16-byte aligned; HT_EINVAL
  * otherwise).  d_out_is_new: n bytes (device), may be NULL when the flags are
  * not wanted.  Grows the table's scratch (allocating, synchronising) when n
- * exceeds what was reserved. */
+ * exceeds what was reserved.  Calls on one table must be ordered by the
+ * caller (one stream, or events between streams), as the table's slots
+ * require anyway: a Cuckoo call of single-word keys leaves the deduplication
+ * slots its winners took for the next such call's first kernel to empty
+ * (state kept on the device, so captured and replayed calls stay exact). */
 int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n,
                    uint8_t* d_out_is_new, hipStream_t stream);
 
 /* For callers that cannot allocate (code under HIP graph capture, tight
  * serving loops, harnesses that forbid allocation): ht_find_or_put that
- * allocates nothing.  Same kernels and results (Sec. 5 find-or-put); the
- * scratch of the Cuckoo insertion (deduplication set, listed keys, per-wave
+ * allocates nothing.  Same results (Sec. 5 find-or-put) and the same probe
+ * and evict kernels, followed by the scrub kernel that empties the
+ * deduplication set before the call returns; the scratch of the Cuckoo
+ * insertion (deduplication set, listed keys, per-wave
  * counts) is a static device array of 8.06 MiB held by each device the
  * library runs on until the process ends, instead of the table's own
  * scratch.  Limits: n <= 262144 keys (HT_EINVAL above), tables of

@@ -205,11 +205,12 @@ int ht_destroy(ht_table* t);
  * vectors of W words each, row-major (n * W words, 16-byte aligned; HT_EINVAL
  * otherwise).  d_out_is_new: n bytes (device), may be NULL when the flags are
  * not wanted.  Grows the table's scratch (allocating, synchronising) when n
- * exceeds what was reserved.  Calls on one table must be ordered by the
- * caller (one stream, or events between streams), as the table's slots
- * require anyway: a Cuckoo call of single-word keys leaves the deduplication
- * slots its winners took for the next such call's first kernel to empty
- * (state kept on the device, so captured and replayed calls stay exact). */
+ * exceeds what was reserved.  Cuckoo and state-vector calls on one table
+ * must be ordered by the caller (one stream, or events between streams):
+ * they share the table's scratch, and a Cuckoo call of single-word keys
+ * leaves the deduplication slots its winners took for the next such call's
+ * first kernel to empty (state kept on the device, so captured and replayed
+ * calls stay exact). */
 int ht_find_or_put(ht_table* t, const uint64_t* d_keys, uint64_t n,
                    uint8_t* d_out_is_new, hipStream_t stream);
 

@@ -151,6 +151,8 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
     uint64_t k[R];
     bool act[R], pend[R], dist[R], lst[R];
     uint32_t em[R];
+    // the flag of each resolved key, stored once after the turn (1 << 8: none)
+    uint32_t fl[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       const uint64_t i = base + (uint64_t)r * kWave + lane;
@@ -160,6 +162,7 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
       dist[r] = pend[r] && hashes_distinct<SCRIPTED>(t, k[r]);
       lst[r] = false;
       em[r] = 0;
+      fl[r] = 1u << 8;
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -171,11 +174,11 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
           res = sentinel_put(t);
           nnew += res;
         }
-        if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
+        fl[r] = res;
       }
       // keys in the stash or the overflow list are found before any placement
       if (pend[r] && (sc | oc) && stash_query(t, k[r], sc, oc)) {
-        if (out) out[base + (uint64_t)r * kWave + lane] = 0;
+        fl[r] = 0;
         pend[r] = false;
       }
     }
@@ -192,7 +195,7 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
         cas[r] = false;
         if (!pend[r]) continue;
         if (v[r] == k[r]) {
-          if (out) out[base + (uint64_t)r * kWave + lane] = 0;
+          fl[r] = 0;
           pend[r] = false;
         } else if (v[r] == kEmpty) {
           if (!dist[r]) {
@@ -214,7 +217,7 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
         if (cas[r] && (old[r] == kEmpty || old[r] == k[r])) {
           const uint32_t res = old[r] == kEmpty ? 1u : 0u;   // placed, or another copy was
           nnew += res;
-          if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
+          fl[r] = res;
           pend[r] = false;
         }
       }
@@ -241,11 +244,16 @@ __device__ __forceinline__ unsigned long long cuckoo_probe_region(const DevTable
           if (go[r] && (old[r] == kEmpty || old[r] == k[r])) {
             const uint32_t res = old[r] == kEmpty ? 1u : 0u;
             nnew += res;
-            if (out) out[base + (uint64_t)r * kWave + lane] = (uint8_t)res;
+            fl[r] = res;
             pend[r] = false;
           }
         }
       }
+    }
+    if (out) {
+#pragma unroll
+      for (int r = 0; r < R; ++r)
+        if (fl[r] < (1u << 8)) out[base + (uint64_t)r * kWave + lane] = (uint8_t)fl[r];
     }
     // every candidate taken (or, in paper order, not found): list for the evict kernel
 #pragma unroll

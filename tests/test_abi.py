@@ -134,3 +134,45 @@ def test_every_entry_point_cites_its_passage_or_says_infrastructure():
         assert re.search(r"Sec\. \d", docs[n]), n
     for n in ("ht_destroy", "ht_stats", "ht_dump_raw", "ht_strerror", "ht_create_simple", "ht_last_error"):
         assert "Infrastructure" in docs[n], n
+
+
+def header_enum_values():
+    """NAME -> value of every HT_* enumerator in include/ht.h (literals and 1u << n)."""
+    src = open(os.path.join(ROOT, "include", "ht.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    vals = {}
+    for name, expr in re.findall(r"\b(HT_[A-Z0-9_]+)\s*=\s*([^,}\n]+)", src):
+        expr = expr.strip()
+        m = re.fullmatch(r"1u\s*<<\s*(\d+)", expr)
+        if m:
+            vals[name] = 1 << int(m.group(1))
+        elif re.fullmatch(r"-?\d+", expr):
+            vals[name] = int(expr)
+    return vals
+
+
+def test_binding_constants_match_header():
+    """Every HT_* constant of the binding equals the header's enumerator, and
+    every flag of the header has its constant in the binding."""
+    vals = header_enum_values()
+    flags = {k for k in vals if k.startswith("HT_FLAG_")}
+    assert {"HT_FLAG_CUCKOO_PAPER_ORDER", "HT_FLAG_BUCKETED_GROUP_QUERY", "HT_FLAG_CUCKOO_LOOKAHEAD"} <= flags
+    for name, v in vals.items():
+        if hasattr(b, name):
+            assert getattr(b, name) == v, name
+    for name in flags:
+        assert getattr(b, name) == vals[name], name
+    # the flags are distinct bits
+    bits = [vals[f] for f in flags]
+    assert len(set(bits)) == len(bits) and all(x & (x - 1) == 0 for x in bits)
+
+
+def test_device_flag_mirrors_match_header():
+    """The device code tests some flags through its own constants; they must be
+    the header's bits."""
+    vals = header_enum_values()
+    src = open(os.path.join(ROOT, "paper_1712_09494_amd", "csrc", "ht_device.h")).read()
+    dev = {n: 1 << int(s) for n, s in re.findall(r"constexpr uint32_t (kFlag\w+) = 1u << (\d+);", src)}
+    assert dev["kFlagChainStats"] == vals["HT_FLAG_CHAIN_STATS"]
+    assert dev["kFlagLookahead"] == vals["HT_FLAG_CUCKOO_LOOKAHEAD"]
+    assert dev["kFlagGroupQuery"] == vals["HT_FLAG_BUCKETED_GROUP_QUERY"]

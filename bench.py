@@ -81,7 +81,7 @@ def parse():
     ap.add_argument("--no-paper", action="store_true", help="skip the paper's own designs on the W2 fill")
     ap.add_argument("--no-mix", action="store_true", help="skip the mixed memory-pattern probes")
     ap.add_argument("--no-evict-profile", action="store_true", help="skip the eviction-chain profile")
-    ap.add_argument("--detail", default=os.path.join(ROOT, "gpurun_out", "bench_detail.json"),
+    ap.add_argument("--detail", default=os.path.join(ROOT, "results", "bench_detail.json"),
                     help="file for the full results (the stdout line carries the headline); '' = none")
     return ap.parse_args()
 

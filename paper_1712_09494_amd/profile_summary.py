@@ -3,8 +3,7 @@ under profiles/ (per-kernel counters per dispatch, HBM traffic scaled by a
 plain copy of known size, and the kernel-trace statistics).
 
     python -m paper_1712_09494_amd.profile_summary --workload random_scaling_2p26 \
-        --pmc gpurun_out/p_fetch gpurun_out/p_write ... --trace gpurun_out/kt \
-        --commands-file gpurun_out/prof_commands.txt
+        --pmc out/pmc1 out/pmc2 ... --trace out/kt --commands-file out/prof_commands.txt
 
 Counter passes: each --pmc directory holds the run_counter_collection.csv of
 one rocprofv3 --pmc run of the same program.  FETCH_SIZE and WRITE_SIZE (KiB

@@ -1216,7 +1216,9 @@ def run_bfs(b, inputs, torch, levels=7, lf=0.7):
             # Cuckoo placing every new key by exchange into h_1 (Sec. 4.1)
             ("bucketed_b16", "bucketed", dict(bucket_slots=16), b.HT_BFS_SPLIT),
             ("cuckoo_paper_order", "cuckoo", dict(flags=b.HT_FLAG_CUCKOO_PAPER_ORDER), b.HT_BFS_SPLIT)):
-        with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=3, **kw) as t:
+        # c = 3 bucketed, c = 4 Cuckoo as in the W2 step (Cuckoo BFS levels: 31.6 against 33.1 ms fused,
+        # 43.7 against 45.8 ms split at c = 3)
+        with b.Table(kind, capacity=int(np.ceil(final_states / lf)), nhash=4 if kind == "cuckoo" else 3, **kw) as t:
             r = b.ht_bfs_explore_ex(t.handle, inputs.BfsModel(1), levels, mode)
             keys = sum(r["batch_sizes"])
             ms = sum(r["fop_ms"])

@@ -59,11 +59,25 @@ def check_visited_set(t, g):
     assert set_digest(dump) == g["visited_digest"][-1]
 
 
-@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+# the bench's BFS configurations: bucketed B = 8, c = 3; Cuckoo c = 4 (and c = 3)
+FULL = [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict()), ("cuckoo", dict(nhash=4))]
+# the bench's other split-level designs: one lane per key, the 128-byte bucket, the Sec. 4.1 order
+FULL_SPLIT = FULL + [("bucketed", dict(bucket_slots=8, flags=b.HT_FLAG_BUCKETED_ONE_LANE)),
+                     ("bucketed", dict(bucket_slots=16)),
+                     ("cuckoo", dict(nhash=4, flags=b.HT_FLAG_CUCKOO_PAPER_ORDER))]
+
+
+def table_args(kw):
+    a = dict(nhash=3)
+    a.update(kw)
+    return a
+
+
+@pytest.mark.parametrize("kind,kw", FULL_SPLIT)
 def test_bfs_full_size_seed1(kind, kw):
     g = golden()["seed1"]
     visited = g["visited_after"]
-    with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, **kw) as t:
+    with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), **table_args(kw)) as t:
         r = t.bfs_explore(inputs.BfsModel(1), 7)
         assert r["batch_sizes"] == g["batch_sizes"]
         assert r["new_counts"] == g["new_counts"]
@@ -136,11 +150,11 @@ def test_bfs_fused_from_all_ones_state(kind, kw):
             assert t.query(torch.tensor([-1], dtype=torch.int64, device="cuda")).item() == 1
 
 
-@pytest.mark.parametrize("kind,kw", [("bucketed", dict(bucket_slots=8)), ("cuckoo", dict())])
+@pytest.mark.parametrize("kind,kw", FULL)
 def test_bfs_fused_full_size_seed1(kind, kw):
     g = golden()["seed1"]
     visited = g["visited_after"]
-    with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), nhash=3, **kw) as t:
+    with b.Table(kind, capacity=int(np.ceil(visited[-1] / 0.7)), **table_args(kw)) as t:
         r = t.bfs_explore(inputs.BfsModel(1), 7, fused=True)
         assert r["batch_sizes"] == g["batch_sizes"]
         assert list(1 + np.cumsum(r["new_counts"])) == visited

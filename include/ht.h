@@ -82,11 +82,11 @@ enum {
    * is first written (compare-and-swap) into a candidate slot that the probe
    * saw empty, and the eviction chain starts only when none is left. */
   HT_FLAG_CUCKOO_PAPER_ORDER = 1u << 0,
-  /* Bucketed, lane groups: read each lane's two slots with two 8-byte
-   * agent-scope atomic loads instead of one 16-byte load.  Results are
+  /* Bucketed, lane groups: read each lane's four slots with four 8-byte
+   * agent-scope atomic loads instead of two 16-byte loads.  Results are
    * identical (a stale empty slot is corrected by the compare-and-swap
-   * result); the 16-byte load touches a bucket with one cache request per
-   * lane group instead of two, and is the default. */
+   * result); the 16-byte loads touch a bucket with half the cache requests,
+   * and are the default. */
   HT_FLAG_BUCKETED_ATOMIC_LOADS = 1u << 1,
   /* Test mode: h_j(key) is taken from a table installed with
    * ht_set_scripted_hash instead of the hash family. */
@@ -107,10 +107,10 @@ enum {
   HT_FLAG_CUCKOO_SINGLE_PASS = 1u << 4,
   /* Bucketed, single-word keys: probe with one lane per key (each lane reads
    * its buckets eight slots at a time and compare-and-swaps the first empty
-   * slot) instead of a group of B/2 lanes sharing each bucket (Sec. 4.2).
+   * slot) instead of a group of B/4 lanes sharing each bucket (Sec. 4.2).
    * Same table, probe sequence and results; a wave serves 64 keys per turn
-   * instead of 128/B.  Faster where hits dominate and the table is cache
-   * resident.  The many-table launch always probes this way. */
+   * instead of 256/B.  Faster where hits dominate (BFS keys, heavy
+   * duplication).  The many-table launch always probes this way. */
   HT_FLAG_BUCKETED_ONE_LANE = 1u << 5,
   /* Measurement: record each Cuckoo eviction chain's number of exchanges in
    * a histogram read by ht_chain_histogram (one extra atomic per chain). */
@@ -139,9 +139,8 @@ typedef struct {
   uint32_t bucket_slots;   /* bucketed: B in {8, 16, 32, 64}; 0 = 16 (one 128-byte
                               line of 64-bit keys).  Ignored by cuckoo */
   uint32_t keys_per_group; /* keys each lane group (bucketed) or lane (cuckoo)
-                              keeps in flight: 1, 2 or 4; 0 = by design
-                              (bucketed B=8: 1, B=16: 2, B>=32: 4; cuckoo: 1).
-                              Bucketed queries use at least 2 */
+                              keeps in flight: 1, 2 or 4; 0 = 1.  Bucketed
+                              lane-group queries use at least 2 */
   uint32_t stash_slots;    /* stash size (power of two, <= 65536); 0 = 1024 */
   uint32_t max_chain;      /* cuckoo eviction bound; 0 = 8 * ceil(log2 capacity) */
   uint64_t seed;           /* seed of the hash constants */

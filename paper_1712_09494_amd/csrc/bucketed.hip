@@ -5,15 +5,24 @@ namespace ht {
 
 // ---- host launchers --------------------------------------------------------
 
+// Find-or-put lane groups of B / 4 lanes, each lane holding four slots (two
+// 16-byte loads).  Against two slots per lane (B / 2 lanes, one load), on the
+// 2^20-key batches of a 2^26-key fill at LF 0.7: B = 8 3.47 against 3.86 ms,
+// B = 16 3.64 against 4.80, B = 32 5.24 against 8.09 (one key per group, 8
+// blocks per compute unit; the two-slot times at their best settings), B = 64
+// 10.3 (6 blocks per unit) against 14.1.
 template <int B, int R>
 static hipError_t launch_fop(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
                              bool coherent, bool scripted, hipStream_t s) {
   if (scripted)
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, 1, true, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, 4, 1, true, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n,
+                       out);
   else if (coherent)
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, 4, R, false, true>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n,
+                       out);
   else
-    hipLaunchKernelGGL((bucketed_fop_kernel<B, R, false, false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n, out);
+    hipLaunchKernelGGL((bucketed_fop_kernel<B, 4, R, false, false>), dim3(grid), dim3(kBlock), t.lds, s, t, keys, n,
+                       out);
   return hipGetLastError();
 }
 
@@ -27,8 +36,8 @@ static hipError_t launch_query(const DevTable& t, const uint64_t* keys, uint64_t
   return hipGetLastError();
 }
 
-// Keys one wave serves per loop turn.
-uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R) { return (128 / B) * R; }
+// Keys one wave serves per loop turn (lane groups of B / spl lanes).
+uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R, uint32_t spl) { return (64 * spl / B) * R; }
 
 #define HT_BUCKET_DISPATCH(CALL)                                   \
   switch (t.bucket_slots * 16 + R) {                               \
@@ -81,3 +90,4 @@ hipError_t bucketed_lane_query(const DevTable& t, const uint64_t* keys, uint64_t
 }
 
 }  // namespace ht
+

@@ -64,11 +64,14 @@ __device__ __forceinline__ uint64_t probe_bucket(const DevTable& t, uint64_t k, 
 
 // Find-or-put of R keys per lane group.  Called by all 64 lanes of a wave;
 // k[r] and active[r] are uniform within a group.  res[r] gets 0/1/2 (ht.h).
-template <int B, int R, bool SCRIPTED, bool COHERENT>
+// A group has L = B / SPL lanes, each holding SPL consecutive slots of the
+// bucket (SPL = 2: one 16-byte load per lane; SPL = 4: two).
+template <int B, int SPL, int R, bool SCRIPTED, bool COHERENT>
 __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint64_t (&k)[R],
                                                    const bool (&active)[R], uint32_t (&res)[R]) {
+  static_assert(SPL == 2 || SPL == 4, "slots per lane");
   const uint32_t Bw = bucket_width<B>(t);
-  const int L = (int)(Bw / 2);
+  const int L = (int)(Bw / SPL);
   const uint64_t gm = lanes_mask((uint32_t)L);
   const int lane = lane_id();
   const int gl = lane & (L - 1);
@@ -76,7 +79,7 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
   const uint32_t nseq = t.nhash + t.walk;   // probe sequence length
   bool done[R], need[R];
   uint32_t j[R];
-  uint64_t b[R], v0[R], v1[R];
+  uint64_t b[R], v[R][SPL];
 #pragma unroll
   for (int r = 0; r < R; ++r) {
     res[r] = 0;
@@ -84,7 +87,8 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
     need[r] = true;
     j[r] = 0;
     b[r] = 0;
-    v0[r] = v1[r] = kEmpty;
+#pragma unroll
+    for (int q = 0; q < SPL; ++q) v[r][q] = kEmpty;
     if (active[r] && k[r] == kEmpty) {     // all-ones key: flag word
       uint32_t won = 0;
       if (gl == 0) won = sentinel_put(t);
@@ -102,23 +106,33 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
     for (int r = 0; r < R; ++r) {
       if (!done[r] && need[r]) {
         b[r] = probe_bucket<SCRIPTED>(t, k[r], j[r], b[r]);
-        load_pair<COHERENT>(t.slots + b[r] * (uint64_t)Bw + 2 * gl, v0[r], v1[r]);
+        const uint64_t* p = t.slots + b[r] * (uint64_t)Bw + SPL * gl;
+#pragma unroll
+        for (int q = 0; q < SPL; q += 2) load_pair<COHERENT>(p + q, v[r][q], v[r][q + 1]);
         need[r] = false;
       }
     }
-    // 2. vote: present / full / lowest empty slot
+    // 2. vote: present / full / lowest empty slot (lowest lane with an empty
+    //    slot, then its lowest empty slot)
     int tgt[R];
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       tgt[r] = -1;
       if (!done[r]) {
-        if (group_bits((v0[r] == k[r]) | (v1[r] == k[r]), g0, gm)) {
+        bool has = false;
+#pragma unroll
+        for (int q = 0; q < SPL; ++q) has |= v[r][q] == k[r];
+        if (group_bits(has, g0, gm)) {
           res[r] = 0;
           done[r] = true;
         } else {
-          const uint64_t e0 = group_bits(v0[r] == kEmpty, g0, gm);
-          const uint64_t e1 = group_bits(v1[r] == kEmpty, g0, gm);
-          const uint64_t ea = e0 | e1;
+          uint64_t e[SPL];
+          uint64_t ea = 0;
+#pragma unroll
+          for (int q = 0; q < SPL; ++q) {
+            e[q] = group_bits(v[r][q] == kEmpty, g0, gm);
+            ea |= e[q];
+          }
           if (ea == 0) {
             if (++j[r] < nseq) {
               need[r] = true;            // bucket full: next bucket of the sequence
@@ -130,7 +144,10 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
             }
           } else {
             const int lf = __builtin_ctzll(ea);
-            tgt[r] = 2 * lf + (((e0 >> lf) & 1ull) ? 0 : 1);
+            int q0 = SPL - 1;
+#pragma unroll
+            for (int q = SPL - 2; q >= 0; --q) q0 = ((e[q] >> lf) & 1ull) ? q : q0;
+            tgt[r] = SPL * lf + q0;
           }
         }
       }
@@ -140,14 +157,14 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       old[r] = 0;
-      if (tgt[r] >= 0 && gl == (tgt[r] >> 1))
+      if (tgt[r] >= 0 && gl == tgt[r] / SPL)
         old[r] = cas64(t.slots + b[r] * (uint64_t)Bw + tgt[r], kEmpty, k[r]);
     }
     // 4. resolve: won, found, or patch the stale copy and retry
 #pragma unroll
     for (int r = 0; r < R; ++r) {
       if (tgt[r] >= 0) {
-        const int owner = tgt[r] >> 1;
+        const int owner = tgt[r] / SPL;
         const uint64_t o = shfl64(old[r], g0 + owner);
         if (o == kEmpty) {
           res[r] = 1;
@@ -156,7 +173,9 @@ __device__ __forceinline__ void bucket_find_or_put(const DevTable& t, const uint
           res[r] = 0;
           done[r] = true;
         } else if (gl == owner) {
-          if (tgt[r] & 1) v1[r] = o; else v0[r] = o;
+          const int qq = tgt[r] % SPL;
+#pragma unroll
+          for (int q = 0; q < SPL; ++q) v[r][q] = q == qq ? o : v[r][q];
         }
       }
     }
@@ -227,11 +246,11 @@ __device__ __forceinline__ void bucket_query(const DevTable& t, const uint64_t (
 // One wave, one turn: find-or-put of keys base .. base + G*R (clipped at
 // end); group g handles keys base + r*G + g (consecutive groups read
 // consecutive keys).  Returns (in group leaders) the number of new keys.
-template <int B, int R, bool SCRIPTED, bool COHERENT>
+template <int B, int SPL, int R, bool SCRIPTED, bool COHERENT>
 __device__ __forceinline__ unsigned long long bucketed_fop_turn(const DevTable& t, const uint64_t* __restrict__ keys,
                                                                 uint64_t base, uint64_t end,
                                                                 uint8_t* __restrict__ out) {
-  const uint32_t L = bucket_width<B>(t) / 2;
+  const uint32_t L = bucket_width<B>(t) / SPL;
   const uint32_t G = kWave / L;
   const int lane = lane_id();
   const int gl = lane & (L - 1);
@@ -245,7 +264,7 @@ __device__ __forceinline__ unsigned long long bucketed_fop_turn(const DevTable& 
     act[r] = i < end;
     k[r] = act[r] ? keys[i] : 0;
   }
-  bucket_find_or_put<B, R, SCRIPTED, COHERENT>(t, k, act, res);
+  bucket_find_or_put<B, SPL, R, SCRIPTED, COHERENT>(t, k, act, res);
   unsigned long long nnew = 0;
   if (gl == 0) {
 #pragma unroll
@@ -260,15 +279,15 @@ __device__ __forceinline__ unsigned long long bucketed_fop_turn(const DevTable& 
 }
 
 // Grid-stride find-or-put: wave w takes turns w, w + nwaves, ...
-template <int B, int R, bool SCRIPTED, bool COHERENT>
+template <int B, int SPL, int R, bool SCRIPTED, bool COHERENT>
 __global__ __launch_bounds__(kBlock) void bucketed_fop_kernel(DevTable t, const uint64_t* __restrict__ keys,
                                                                uint64_t n, uint8_t* __restrict__ out) {
-  constexpr uint64_t PER = (uint64_t)BucketGeo<B>::G * R;
+  constexpr uint64_t PER = (uint64_t)(kWave / (B / SPL)) * R;
   const uint64_t wave = ((uint64_t)blockIdx.x * kBlock + threadIdx.x) / kWave;
   const uint64_t nwaves = (uint64_t)gridDim.x * (kBlock / kWave);
   unsigned long long nnew = 0;
   for (uint64_t base = wave * PER; base < n; base += nwaves * PER)
-    nnew += bucketed_fop_turn<B, R, SCRIPTED, COHERENT>(t, keys, base, n, out);
+    nnew += bucketed_fop_turn<B, SPL, R, SCRIPTED, COHERENT>(t, keys, base, n, out);
   wave_count(t.ctr->size, nnew, (uint32_t)wave);
 }
 

@@ -18,7 +18,9 @@ hipError_t bucketed_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint
                                 bool, hipStream_t);
 hipError_t bucketed_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, uint32_t, bool,
                           hipStream_t);
-uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R);
+uint64_t bucketed_keys_per_wave(uint32_t B, uint32_t R, uint32_t spl);
+// slots each lane of a find-or-put lane group holds (bucketed.hip)
+constexpr uint32_t kFopSlotsPerLane = 4;
 hipError_t bucketed_lane_find_or_put(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool,
                                      hipStream_t);
 hipError_t bucketed_lane_query(const DevTable&, const uint64_t*, uint64_t, uint8_t*, uint32_t, bool, hipStream_t);
@@ -370,11 +372,10 @@ void setup_geometry(ht_table* t) {
   if (!c.stash_slots) c.stash_slots = 1024;
   if (!c.overflow_slots) c.overflow_slots = 65536;
   if (!c.max_chain) c.max_chain = 8 * std::max<uint32_t>(1, ceil_log2(t->nslots));
-  if (!c.keys_per_group) {
-    // measured best per bucket width (B = 8: 16 keys per wave already)
-    if (c.kind == HT_CUCKOO) c.keys_per_group = 1;
-    else c.keys_per_group = c.bucket_slots <= 8 ? 1 : (c.bucket_slots == 16 ? 2 : 4);
-  }
+  // one key per lane group or lane: measured best for Cuckoo and, with four
+  // slots per lane, for every bucket width (2^26-key fill at LF 0.7: B = 16
+  // 3.64 ms at 1 key per group against 4.13 at 2; B = 32 5.24 against 5.84)
+  if (!c.keys_per_group) c.keys_per_group = 1;
   t->dev.nhash = c.nhash;
   t->dev.bucket_slots = c.bucket_slots;
   t->dev.stash_slots = c.stash_slots;
@@ -504,7 +505,7 @@ int do_find_or_put(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, 
     return HT_OK;
   }
   if (t->cfg.kind == HT_BUCKETED) {
-    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R);
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, R, kFopSlotsPerLane);
     const uint64_t waves = (n + g - 1) / g;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_fop", s);
@@ -585,7 +586,7 @@ int do_query(ht_table* t, const uint64_t* keys, uint64_t n, uint8_t* out, hipStr
     // a query issues no atomics, so a second key in flight per group pays off
     // even where find-or-put prefers one (measured: +11-14% at B = 8 and 16)
     const uint32_t Rq = R < 2 ? 2 : R;
-    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, Rq);
+    const uint64_t g = bucketed_keys_per_wave(t->cfg.bucket_slots, Rq, 2);
     const uint64_t waves = (n + g - 1) / g;
     const uint64_t blocks = std::min<uint64_t>((waves + 3) / 4, max_blocks(t));
     KernelTimer kt("bucketed_query", s);

@@ -7,10 +7,11 @@
 // bucket moves on to h_2, ...; when all c buckets are full the table is full.
 // Sec. 5.1.2 reduces the element to one word per key, as here.
 //
-// wave64 layout: a bucket of B 64-bit slots is read by a group of L = B/2
-// lanes, each loading 16 bytes, so one wave serves 128/B keys per step
-// (B = 16: a 128-byte line, 8 keys per wave).  Votes are 64-bit ballots cut
-// to the group's L bits; the compare-and-swap is issued by the lane that owns
+// wave64 layout: a bucket of B 64-bit slots is read by a group of L lanes.
+// Find-or-put: L = B/4, each lane loading four slots with two 16-byte loads,
+// so one wave serves 256/B keys per step (B = 8: 32 keys).  Lane-group query:
+// L = B/2, one 16-byte load per lane.  Votes are 64-bit ballots cut to the
+// group's L bits; the compare-and-swap is issued by the lane that owns
 // the chosen slot and its result is broadcast to the group.  Each group keeps
 // R keys in flight: every loop turn first issues the bucket loads of all R
 // keys, then evaluates them, then issues all their compare-and-swaps, then

@@ -98,7 +98,7 @@ def test_bfs_full_size_seed2(kind, kw):
 
 
 FUSED = [("bucketed", dict(bucket_slots=8)), ("bucketed", dict(bucket_slots=16)),
-         ("bucketed", dict(bucket_slots=64, nhash=2)),
+         ("bucketed", dict(bucket_slots=32, nhash=4)), ("bucketed", dict(bucket_slots=64, nhash=2)),
          ("bucketed", dict(bucket_slots=16, flags=b.HT_FLAG_BUCKETED_PAPER_FULL)),
          ("cuckoo", dict()), ("cuckoo", dict(nhash=4)), ("cuckoo", dict(nhash=2)),
          ("cuckoo", dict(flags=b.HT_FLAG_CUCKOO_PAPER_ORDER))]

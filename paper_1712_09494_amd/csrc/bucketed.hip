@@ -8,9 +8,9 @@ namespace ht {
 // Find-or-put lane groups of B / 4 lanes, each lane holding four slots (two
 // 16-byte loads).  Against two slots per lane (B / 2 lanes, one load), on the
 // 2^20-key batches of a 2^26-key fill at LF 0.7: B = 8 3.47 against 3.86 ms,
-// B = 16 3.64 against 4.80, B = 32 5.24 against 8.09 (one key per group, 8
-// blocks per compute unit; the two-slot times at their best settings), B = 64
-// 10.3 (6 blocks per unit) against 14.1.
+// B = 16 3.64 against 4.80, B = 32 5.24 against 8.09, B = 64 8.75 against
+// 14.1 (one key per group, 8 blocks per compute unit; the two-slot times at
+// their best settings).
 template <int B, int R>
 static hipError_t launch_fop(const DevTable& t, const uint64_t* keys, uint64_t n, uint8_t* out, uint32_t grid,
                              bool coherent, bool scripted, hipStream_t s) {

@@ -179,8 +179,9 @@ uint32_t max_blocks(const ht_table* t) { return t->cus * 8; }
 // 2^26-key fill at c = 4 (probe kernel, average per launch): 73.9 us at 8
 // blocks per unit, 67.7 at 7, 66.6 at 6, 70.2 at 5, 67.5 at 4; 2^24 state
 // vectors in batches of 2^20: 5-7% faster at 6 than at 8 for both designs
-// and W = 2, 4.  The bucketed lane-group kernel is fastest at 8 (fill 3.88 ms
-// at 8, 4.05 at 7, 4.33 at 6), and so is the many-table bucketed fill (256
+// and W = 2, 4.  The bucketed lane-group kernel is fastest at 8 (two slots
+// per lane: fill 3.88 ms at 8, 4.05 at 7, 4.33 at 6; four slots per lane at
+// B = 64: 8.75 at 8, 10.3 at 6), and so is the many-table bucketed fill (256
 // tables: 5.73 ms at 8, 5.92 at 6).
 uint32_t atomic_grid_blocks(const ht_table* t) { return t->cus * 6; }
 
@@ -372,9 +373,10 @@ void setup_geometry(ht_table* t) {
   if (!c.stash_slots) c.stash_slots = 1024;
   if (!c.overflow_slots) c.overflow_slots = 65536;
   if (!c.max_chain) c.max_chain = 8 * std::max<uint32_t>(1, ceil_log2(t->nslots));
-  // one key per lane group or lane: measured best for Cuckoo and, with four
-  // slots per lane, for every bucket width (2^26-key fill at LF 0.7: B = 16
-  // 3.64 ms at 1 key per group against 4.13 at 2; B = 32 5.24 against 5.84)
+  // one key per lane group or lane: measured best for Cuckoo (2^26-key fill
+  // at LF 0.7, c = 4: 5.88 ms at 1 key per lane, 5.96 at 2, 6.20 at 4) and,
+  // with four slots per lane, for every bucket width (B = 16 3.64 ms at 1 key
+  // per group against 4.13 at 2; B = 32 5.24 against 5.84)
   if (!c.keys_per_group) c.keys_per_group = 1;
   t->dev.nhash = c.nhash;
   t->dev.bucket_slots = c.bucket_slots;

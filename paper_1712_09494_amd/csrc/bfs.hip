@@ -36,6 +36,7 @@
 #include "runtime.h"
 
 namespace ht {
+hipError_t zero_words(uint32_t*, uint64_t, hipStream_t);
 hipError_t scan_exclusive(const unsigned long long*, unsigned long long*, uint64_t, unsigned long long*,
                           unsigned long long*, uint32_t, hipStream_t);
 hipError_t select_flagged(const uint64_t*, const uint8_t*, uint64_t, uint64_t*, unsigned long long*,
@@ -450,7 +451,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
     auto* ns = static_cast<unsigned long long*>(nsel.p);
     auto* mk = static_cast<uint64_t*>(masks.p);
     const uint32_t g1 = (uint32_t)std::min<uint64_t>((nf + kBlock - 1) / kBlock, grid);
-    if (fused && !ck) HT_HIP(hipMemsetAsync(ns, 0, 8, s));
+    if (fused && !ck) HT_HIP(zero_words(reinterpret_cast<uint32_t*>(ns), 2, s));
     double lms = 0.0;
     // span 1: successor counts (split, fused Cuckoo) or the fused bucketed pass, then a scan
     HT_HIP(hipEventRecord(ev[0], s));

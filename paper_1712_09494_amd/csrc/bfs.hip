@@ -90,15 +90,63 @@ __device__ __forceinline__ void for_each_successor(const BfsModelDev& m, uint64_
   }
 }
 
-// Split pass: every successor, written at the state's scanned offset.
+// Writing a level's successors (all of them, or those a mask marks) at the
+// states' scanned offsets, staged through LDS so that the stores coalesce:
+// a block takes a tile of kBlock consecutive states, whose outputs form one
+// contiguous range; each thread places its state's successors that fall in
+// the current window of kWriteWin positions, then the block copies the
+// window out in consecutive words.  A thread per state storing its own
+// successors one after another wrote 8-byte words to 64 unrelated places per
+// instruction: 7.7 ms for the 5.7 GB batch of the 7-level workload's last
+// level.
+constexpr uint32_t kWriteWin = 2048;
+
+template <bool MASKED>
+__device__ __forceinline__ void write_tiles(const BfsModelDev& m, const uint64_t* __restrict__ f, uint64_t nf,
+                                            const unsigned long long* __restrict__ cnt,
+                                            const unsigned long long* __restrict__ off,
+                                            const uint64_t* __restrict__ mask, uint64_t* __restrict__ out) {
+  __shared__ uint64_t win[kWriteWin];
+  const uint32_t tid = threadIdx.x;
+  for (uint64_t i0 = (uint64_t)blockIdx.x * kBlock; i0 < nf; i0 += (uint64_t)gridDim.x * kBlock) {
+    const uint64_t last = (i0 + kBlock < nf ? i0 + kBlock : nf) - 1;
+    const uint64_t base = off[i0];
+    const uint64_t end = off[last] + cnt[last];
+    const uint64_t i = i0 + tid;
+    const bool live = i < nf;
+    const uint64_t st = live ? f[i] : 0ull;
+    const uint64_t mine = live ? off[i] : 0ull;
+    const uint64_t myend = live ? mine + cnt[i] : 0ull;
+    const uint64_t m0 = MASKED && live ? mask[2 * i] : ~0ull;
+    const uint64_t m1 = MASKED && live ? mask[2 * i + 1] : ~0ull;
+    for (uint64_t w = base; w < end; w += kWriteWin) {
+      if (live && mine < w + kWriteWin && myend > w) {
+        uint64_t o = mine;
+        uint32_t k = 0;
+        for_each_successor(m, st, [&](uint64_t succ) {
+          const bool take = !MASKED || (((k < 64 ? (m0 >> k) : (m1 >> (k - 64))) & 1ull) != 0);
+          ++k;
+          if (take) {
+            if (o >= w && o < w + kWriteWin) win[o - w] = succ;
+            ++o;
+          }
+        });
+      }
+      __syncthreads();
+      const uint64_t nw = end - w < kWriteWin ? end - w : kWriteWin;
+      for (uint32_t j = tid; j < nw; j += kBlock) out[w + j] = win[j];
+      __syncthreads();
+    }
+  }
+}
+
+// Split pass: every successor, written at the state's scanned offset (cnt:
+// successors per state, off: their exclusive scan).
 __global__ __launch_bounds__(kBlock) void bfs_write_kernel(BfsModelDev m, const uint64_t* __restrict__ f, uint64_t nf,
+                                                           const unsigned long long* __restrict__ cnt,
                                                            const unsigned long long* __restrict__ off,
                                                            uint64_t* __restrict__ out) {
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nf; i += stride) {
-    uint64_t o = off[i];
-    for_each_successor(m, f[i], [&](uint64_t succ) { out[o++] = succ; });
-  }
+  write_tiles<false>(m, f, nf, cnt, off, nullptr, out);
 }
 
 // Fused pass: find-or-put of every successor of the frontier; per state the
@@ -134,22 +182,14 @@ __global__ __launch_bounds__(kBlock) void bfs_fused_kernel(BfsModelDev m, DevTab
   if (lane_id() == 0 && g) add_agent(generated, g);
 }
 
-// Second fused pass: the successors marked new, written at the scanned offsets.
+// Second fused pass: the successors marked new, written at the scanned
+// offsets (cnt: new successors per state, off: their exclusive scan).
 __global__ __launch_bounds__(kBlock) void bfs_fused_write_kernel(BfsModelDev m, const uint64_t* __restrict__ f,
                                                                  uint64_t nf, const uint64_t* __restrict__ mask,
+                                                                 const unsigned long long* __restrict__ cnt,
                                                                  const unsigned long long* __restrict__ off,
                                                                  uint64_t* __restrict__ out) {
-  const uint64_t stride = (uint64_t)gridDim.x * kBlock;
-  for (uint64_t i = (uint64_t)blockIdx.x * kBlock + threadIdx.x; i < nf; i += stride) {
-    const uint64_t m0 = mask[2 * i], m1 = mask[2 * i + 1];
-    if (!(m0 | m1)) continue;
-    uint64_t o = off[i];
-    uint32_t k = 0;
-    for_each_successor(m, f[i], [&](uint64_t succ) {
-      if ((k < 64 ? (m0 >> k) : (m1 >> (k - 64))) & 1) out[o++] = succ;
-      ++k;
-    });
-  }
+  write_tiles<true>(m, f, nf, cnt, off, mask, out);
 }
 
 // Successors of one state, one per call, in model order (the same order as
@@ -517,7 +557,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       if (rc) break;
       const unsigned long long* woff = ck ? static_cast<const unsigned long long*>(noffsets.p) : off;
       HT_HIP(hipEventRecord(ev[4], s));
-      hipLaunchKernelGGL(bfs_fused_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, mk, woff,
+      hipLaunchKernelGGL(bfs_fused_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, mk, cnt, woff,
                          static_cast<uint64_t*>(next.p));
       HT_HIP(hipGetLastError());
       HT_HIP(hipEventRecord(ev[5], s));
@@ -534,7 +574,7 @@ extern "C" int ht_bfs_explore_ex(ht_table* t, const ht_bfs_model* model, uint64_
       auto* fl = static_cast<uint8_t*>(flags.p);
       // span 2: write the batch, find-or-put it, select the new keys
       HT_HIP(hipEventRecord(ev[2], s));
-      hipLaunchKernelGGL(bfs_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, off, bt);
+      hipLaunchKernelGGL(bfs_write_kernel, dim3(g1), dim3(kBlock), 0, s, m, fr, nf, cnt, off, bt);
       HT_HIP(hipGetLastError());
       HT_HIP(hipEventRecord(ev[6], s));
       rc = do_find_or_put(t, bt, nb, fl, s);
